@@ -1,0 +1,163 @@
+/*
+ * met_bp.h -- C ABI of the MI355X (gfx950) syndrome belief-propagation decoder
+ * for multi-edge-type (MET) LDPC codes.
+ *
+ * Method: Wang, Zhang, Yu, Guo, "High speed error correction for
+ * continuous-variable quantum key distribution with multi-edge type LDPC code"
+ * (arXiv:1711.01783).  The decoder is the flooding sum-product algorithm of the
+ * Methods section (Steps 1-5, eq. (1)-(5)), run in log-likelihood ratios (last
+ * Methods paragraph) on many codewords at once (Results, "High speed error
+ * correction with MET-LDPC codes"), with degree-1 variable nodes left out of
+ * the iterations (same passage; Discussion; Table 1 note 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Return value: 0 (MET_OK) or a negative MET_E* code; the text of the last
+ *   error of the calling thread is available from met_last_error().  No entry
+ *   point aborts the process.  Arguments are validated before any HIP call, so
+ *   argument errors are reported identically on machines without a GPU.
+ * Ownership: the caller owns every buffer it passes.  The library owns only a
+ *   code handle (host adjacency plus one device copy per GPU it was used on)
+ *   until met_code_free().  "dev" marks device pointers (HIP device memory of
+ *   the current device), "host" marks host pointers.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Device work
+ *   is enqueued asynchronously on it; outputs are valid once it has drained.
+ * LLR sign: L = ln p(x=0)/p(x=1), i.e. L = -ln q0 with the paper's ratio
+ *   q0 = p(1)/p(0) of eq. (1).  A hard decision is 1 iff the posterior is < 0
+ *   (Step 5: c = 1 iff q > 1); a posterior of exactly 0 gives 0.
+ * Layouts: frame-major row arrays; llr and posterior are float32 [B][N] in the
+ *   code's variable-node order, bits uint8 [B][N] (0/1), syndromes uint8 [B][M]
+ *   (0/1) in the code's check order.
+ * Concurrency: calls on different streams with different workspaces may run
+ *   concurrently; a workspace must not be shared by overlapping calls.
+ */
+#ifndef MET_BP_H
+#define MET_BP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MET_OK 0
+#define MET_EINVAL (-1)   /* bad argument: null/misaligned pointer, size, profile */
+#define MET_ENOMEM (-2)   /* host or device allocation failed */
+#define MET_EHIP (-3)     /* a HIP runtime call failed; see met_last_error() */
+#define MET_ESTATE (-4)   /* call not valid in the current state */
+
+/* met_decode flags */
+#define MET_EARLY_EXIT 0u   /* default: a frame stops at the first iteration whose
+                               hard decision satisfies its syndrome (Step 5) */
+#define MET_FIXED_ITERS 1u  /* every frame runs max_iter iterations; converged
+                               reports the syndrome test after the last one */
+
+#define MET_MAX_EDGE_TYPES 8
+#define MET_MAX_CHECK_DEGREE 32
+
+typedef struct met_code met_code; /* opaque */
+
+/* A MET degree profile (Methods: MET-LDPC codes generalise LDPC codes; the
+ * paper's distributions are from its reference [WANGRA] and not reproduced).
+ * Rows are node types; vn_deg / cn_deg are row-major [n_types][n_edge_types]
+ * degree matrices; fractions are relative to N.  Variable-node counts follow
+ * the fractions (floor, last type takes the remainder); check counts follow
+ * from socket balance and cn_frac must agree with them within 1 % of N. */
+typedef struct {
+  int32_t n_edge_types;
+  int32_t n_vn_types;
+  const double *vn_frac;  /* host [n_vn_types] */
+  const int32_t *vn_deg;  /* host [n_vn_types * n_edge_types] */
+  int32_t n_cn_types;
+  const double *cn_frac;  /* host [n_cn_types] */
+  const int32_t *cn_deg;  /* host [n_cn_types * n_edge_types] */
+} met_profile;
+
+/* Bookkeeping in the terms of Table 1 of the paper. */
+typedef struct {
+  int64_t N, M, E;                   /* variable nodes, checks, edges */
+  int64_t E_type[MET_MAX_EDGE_TYPES];
+  int64_t n_deg1;                    /* degree-1 variable nodes ("ignored VNs") */
+  int64_t edges_to_pass;             /* E - n_deg1 (Table 1 note 2) */
+  int64_t n_msg_vn;                  /* variable nodes of degree != 1 */
+  int64_t n_msg_edges;               /* edges to variable nodes of degree >= 2 */
+  int64_t n_leaf_edges;              /* edges to degree-1 variable nodes */
+  int32_t n_edge_types;
+  int32_t n_check_classes;           /* runs of checks decoded by one kernel shape */
+  int32_t max_check_degree;
+  int32_t max_vn_degree;
+} met_code_stats;
+
+/* Builds a code from a degree profile: per edge type, a seeded random
+ * permutation of check sockets (SplitMix64 + Fisher-Yates), repaired so that no
+ * variable/check pair repeats, then sorted by (check, edge type, variable).
+ * The paper uses progressive edge growth instead (Methods, first paragraph);
+ * this construction is the project's substitute.  Host-only: needs no GPU.
+ * p: host profile; N >= 2; *out receives a new handle.
+ * Errors: MET_EINVAL for an inconsistent profile (edge type in two check types,
+ * unbalanceable sockets, check degree < 2 or > MET_MAX_CHECK_DEGREE, failed
+ * multi-edge repair), MET_ENOMEM. */
+int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out);
+
+/* A code from an explicit edge list (E edges, host arrays, any order; etype may
+ * be NULL for a single edge type).  Used for small hand-built codes in tests.
+ * Errors: MET_EINVAL for out-of-range indices, repeated pairs, a check of
+ * degree < 2 or > MET_MAX_CHECK_DEGREE. */
+int met_code_from_edges(int64_t N, int64_t M, int64_t E, const int32_t *vn, const int32_t *cn,
+                        const int8_t *etype, met_code **out);
+
+/* Fills *out (host).  Errors: MET_EINVAL on NULL. */
+int met_code_info(const met_code *c, met_code_stats *out);
+
+/* Copies the edge list in check order into host arrays of length E.  Any of
+ * vn / cn / etype may be NULL.  Errors: MET_EINVAL on a NULL code. */
+int met_code_export(const met_code *c, int32_t *vn, int32_t *cn, int8_t *etype);
+
+/* Releases the handle and its device copies (NULL is ignored).  The caller
+ * must ensure no queued work still uses the code. */
+void met_code_free(met_code *c);
+
+/* Syndrome S = H x mod 2 for B frames (Step 1: Bob's syndrome S_B = H U).
+ * bits: dev uint8 [B][N] (0/1); syn: dev uint8 [B][M] output.
+ * The first call on a device uploads the adjacency (allocates device memory).
+ * Errors: MET_EINVAL (NULL pointer, B < 1), MET_EHIP. */
+int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, uint8_t *syn, void *stream);
+
+/* Workspace size in bytes that met_decode needs for this code, B frames and
+ * these flags (want_posterior != 0 when a posterior output will be passed).
+ * Errors: MET_EINVAL. */
+int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int32_t want_posterior,
+                               size_t *bytes);
+
+/* Decodes B frames against their syndromes: flooding sum-product BP of the
+ * Methods section -- Step 2 / eq. (1) initialisation from channel LLRs, Step 3 /
+ * eq. (2)-(3) check update with the sign of the target syndrome bit, Step 4 /
+ * eq. (4) variable update of variable nodes of degree >= 2 only, Step 5 /
+ * eq. (5) posteriors, hard decision and syndrome test.  Degree-1 variable nodes
+ * never enter the iterations; their posteriors are formed from their check's
+ * message when needed (Results; Table 1 note 1).
+ *   llr:       dev float32 [B][N], 4-byte aligned
+ *   syn:       dev uint8   [B][M]
+ *   max_iter:  >= 1
+ *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS
+ *   bits:      dev uint8 [B][N] output, hard decisions at each frame's stop
+ *   iters:     dev int32 [B] output, iterations run (1..max_iter)
+ *   converged: dev uint8 [B] output, 1 iff H bits = syn
+ *   posterior: dev float32 [B][N] output, or NULL
+ *   workspace: dev, 256-byte aligned, at least met_decode_workspace_bytes();
+ *              its contents need not be initialised
+ * The first call on a device uploads the adjacency (allocates); later calls
+ * allocate nothing.  Errors: MET_EINVAL, MET_EHIP. */
+int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
+               uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
+               void *workspace, size_t ws_bytes, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *met_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MET_BP_H */

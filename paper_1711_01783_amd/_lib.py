@@ -1,0 +1,89 @@
+"""ctypes declarations of the C ABI (include/met_bp.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libmetbp.so")
+
+MET_OK = 0
+MET_EINVAL = -1
+MET_ENOMEM = -2
+MET_EHIP = -3
+MET_ESTATE = -4
+MET_EARLY_EXIT = 0
+MET_FIXED_ITERS = 1
+MET_MAX_EDGE_TYPES = 8
+
+_ERRNAMES = {MET_EINVAL: "MET_EINVAL", MET_ENOMEM: "MET_ENOMEM", MET_EHIP: "MET_EHIP", MET_ESTATE: "MET_ESTATE"}
+
+
+class MetError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "MET_E?"), code, msg))
+        self.code = code
+
+
+class met_profile(ctypes.Structure):
+    _fields_ = [
+        ("n_edge_types", ctypes.c_int32),
+        ("n_vn_types", ctypes.c_int32),
+        ("vn_frac", ctypes.POINTER(ctypes.c_double)),
+        ("vn_deg", ctypes.POINTER(ctypes.c_int32)),
+        ("n_cn_types", ctypes.c_int32),
+        ("cn_frac", ctypes.POINTER(ctypes.c_double)),
+        ("cn_deg", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+class met_code_stats(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64),
+        ("M", ctypes.c_int64),
+        ("E", ctypes.c_int64),
+        ("E_type", ctypes.c_int64 * MET_MAX_EDGE_TYPES),
+        ("n_deg1", ctypes.c_int64),
+        ("edges_to_pass", ctypes.c_int64),
+        ("n_msg_vn", ctypes.c_int64),
+        ("n_msg_edges", ctypes.c_int64),
+        ("n_leaf_edges", ctypes.c_int64),
+        ("n_edge_types", ctypes.c_int32),
+        ("n_check_classes", ctypes.c_int32),
+        ("max_check_degree", ctypes.c_int32),
+        ("max_vn_degree", ctypes.c_int32),
+    ]
+
+
+def _load():
+    if not os.path.exists(library_path):
+        raise ImportError(
+            "libmetbp.so is not built (expected at %s); run `python -m paper_1711_01783_amd.build`" % library_path
+        )
+    L = ctypes.CDLL(library_path)
+    P = ctypes.c_void_p
+    i32, i64, u32, u64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "met_code_build": (ctypes.c_int, [ctypes.POINTER(met_profile), i64, u64, ctypes.POINTER(P)]),
+        "met_code_from_edges": (ctypes.c_int, [i64, i64, i64, P, P, P, ctypes.POINTER(P)]),
+        "met_code_info": (ctypes.c_int, [P, ctypes.POINTER(met_code_stats)]),
+        "met_code_export": (ctypes.c_int, [P, P, P, P]),
+        "met_code_free": (None, [P]),
+        "met_syndrome": (ctypes.c_int, [P, P, i32, P, P]),
+        "met_decode_workspace_bytes": (ctypes.c_int, [P, i32, u32, i32, ctypes.POINTER(sz)]),
+        "met_decode": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, P]),
+        "met_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def check(rc: int) -> None:
+    if rc != MET_OK:
+        raise MetError(rc, lib.met_last_error().decode())

@@ -1,0 +1,168 @@
+"""Python-level API: code handles, syndrome and decode (argument marshalling)."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._lib import MET_FIXED_ITERS, check, lib, met_code_stats, met_profile
+
+
+class Code:
+    """An owned ``met_code`` handle."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        st = met_code_stats()
+        check(lib.met_code_info(self._h, ctypes.byref(st)))
+        self.N = int(st.N)
+        self.M = int(st.M)
+        self.E = int(st.E)
+        self._stats = st
+
+    @classmethod
+    def build(cls, profile, n: int, seed: int) -> "Code":
+        """From a degree profile with ``vn_types`` / ``cn_types`` rows of
+        (fraction, per-edge-type degrees)."""
+        t = len(profile.vn_types[0][1])
+        vfrac = (ctypes.c_double * len(profile.vn_types))(*[f for f, _ in profile.vn_types])
+        vdeg = (ctypes.c_int32 * (len(profile.vn_types) * t))(*[d for _, ds in profile.vn_types for d in ds])
+        cfrac = (ctypes.c_double * len(profile.cn_types))(*[f for f, _ in profile.cn_types])
+        cdeg = (ctypes.c_int32 * (len(profile.cn_types) * t))(*[d for _, ds in profile.cn_types for d in ds])
+        p = met_profile(t, len(profile.vn_types), vfrac, vdeg, len(profile.cn_types), cfrac, cdeg)
+        h = ctypes.c_void_p()
+        check(lib.met_code_build(ctypes.byref(p), int(n), int(seed) & (2**64 - 1), ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_edges(cls, n: int, m: int, vn, cn, etype=None) -> "Code":
+        vn = np.ascontiguousarray(vn, dtype=np.int32)
+        cn = np.ascontiguousarray(cn, dtype=np.int32)
+        et = None if etype is None else np.ascontiguousarray(etype, dtype=np.int8)
+        h = ctypes.c_void_p()
+        check(
+            lib.met_code_from_edges(
+                int(n), int(m), int(vn.size), vn.ctypes.data, cn.ctypes.data,
+                None if et is None else et.ctypes.data, ctypes.byref(h),
+            )
+        )
+        return cls(h)
+
+    def info(self) -> dict:
+        st = self._stats
+        return {
+            "N": int(st.N),
+            "M": int(st.M),
+            "E": int(st.E),
+            "E_type": [int(st.E_type[k]) for k in range(int(st.n_edge_types))],
+            "n_deg1": int(st.n_deg1),
+            "edges_to_pass": int(st.edges_to_pass),
+            "n_msg_vn": int(st.n_msg_vn),
+            "n_msg_edges": int(st.n_msg_edges),
+            "n_leaf_edges": int(st.n_leaf_edges),
+            "n_edge_types": int(st.n_edge_types),
+            "n_check_classes": int(st.n_check_classes),
+            "max_check_degree": int(st.max_check_degree),
+            "max_vn_degree": int(st.max_vn_degree),
+        }
+
+    def export(self):
+        """(vn int32 [E], cn int32 [E], etype int8 [E]) in check order."""
+        vn = np.empty(self.E, dtype=np.int32)
+        cn = np.empty(self.E, dtype=np.int32)
+        et = np.empty(self.E, dtype=np.int8)
+        check(lib.met_code_export(self._h, vn.ctypes.data, cn.ctypes.data, et.ctypes.data))
+        return vn, cn, et
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib.met_code_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream_ptr(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require(t, dtype, shape, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def syndrome(code: Code, bits, stream=None):
+    """H x mod 2 on the GPU: bits uint8 [B, N] -> uint8 [B, M]."""
+    import torch
+
+    b = int(bits.shape[0])
+    _require(bits, torch.uint8, (b, code.N), "bits")
+    out = torch.empty((b, code.M), dtype=torch.uint8, device=bits.device)
+    check(lib.met_syndrome(code.handle, bits.data_ptr(), b, out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
+def workspace_bytes(code: Code, frames: int, fixed_iters: bool = False, posterior: bool = False) -> int:
+    n = ctypes.c_size_t()
+    flags = MET_FIXED_ITERS if fixed_iters else 0
+    check(lib.met_decode_workspace_bytes(code.handle, int(frames), flags, int(bool(posterior)), ctypes.byref(n)))
+    return int(n.value)
+
+
+@dataclass
+class DecodeOutput:
+    bits: "object"       # uint8 [B, N]
+    iterations: "object" # int32 [B]
+    converged: "object"  # uint8 [B]
+    posterior: "object"  # float32 [B, N] or None
+
+
+def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, posterior: bool = False,
+           workspace=None, stream=None) -> DecodeOutput:
+    """Decode llr float32 [B, N] against syn uint8 [B, M] (device tensors)."""
+    import torch
+
+    b = int(llr.shape[0])
+    dev = llr.device
+    _require(llr, torch.float32, (b, code.N), "llr")
+    _require(syn, torch.uint8, (b, code.M), "syn")
+    need = workspace_bytes(code, b, fixed_iters, posterior)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-workspace.data_ptr()) % 256
+    ws_ptr = workspace.data_ptr() + off
+    ws_len = workspace.numel() - off
+    bits = torch.empty((b, code.N), dtype=torch.uint8, device=dev)
+    iters = torch.empty(b, dtype=torch.int32, device=dev)
+    conv = torch.empty(b, dtype=torch.uint8, device=dev)
+    post = torch.empty((b, code.N), dtype=torch.float32, device=dev) if posterior else None
+    check(
+        lib.met_decode(
+            code.handle, llr.data_ptr(), syn.data_ptr(), b, int(max_iter),
+            MET_FIXED_ITERS if fixed_iters else 0,
+            bits.data_ptr(), iters.data_ptr(), conv.data_ptr(),
+            None if post is None else post.data_ptr(),
+            ctypes.c_void_p(ws_ptr), ws_len, _stream_ptr(stream),
+        )
+    )
+    return DecodeOutput(bits, iters, conv, post)

@@ -1,0 +1,981 @@
+// MI355X (gfx950) kernels and launch orchestration of the syndrome BP decoder.
+//
+// Algorithm: flooding sum-product belief propagation of the paper's Methods
+// section (Steps 2-5, eq. (1)-(5)) in log-likelihood ratios, decoding B frames
+// at once (Results, "High speed error correction with MET-LDPC codes").
+//
+// Formulation used on the GPU ("posterior form"): per message edge e = (v, j)
+// the kernels keep only the check-to-variable message c2v_e, and per
+// variable node of degree >= 2 its posterior P_v.  The variable-to-check
+// message of eq. (4) is re-formed where it is consumed, v2c_e = P_v - c2v_e,
+// which is eq. (4) in logarithms (L_v plus all incoming messages but e's own).
+// Initialisation (Step 2, eq. (1)): P_v = L_v and c2v = 0.
+//
+// Check update (Step 3, eq. (2)-(3)) in the phi domain, phi(x) = ln coth(x/2):
+//   |c2v_e| = phi( sum_{e' != e} phi(|x_e'|) ),  x = clamp(v2c, +-30)
+//   sign(c2v_e) = (-1)^{s_j} * prod_{e' != e} sign(x_e')
+// (the syndrome bit flips the sign: the decoder's target is Bob's syndrome,
+// Step 1 and Step 5).  Leave-one-out sums use prefix/suffix sums, never a
+// subtraction.  Degree-1 variable nodes ("leaves") never enter the iterations
+// (Results; Table 1 note 1): their message into the check is the channel LLR,
+// precomputed once as phi(|L|) with L's sign.
+//
+// Variable update (Step 4, eq. (4)-(5)): P_v = L_v + sum_e c2v_e over v's
+// message edges, summed in a fixed order (deterministic).
+//
+// Syndrome test (Step 5) in early-exit mode: the check kernel of iteration l
+// also evaluates H c = s for iteration l-1 from the signs of P^{l-1} and the
+// stored leaf decisions of l-1, so the test costs no extra pass; the variable
+// kernel of iteration l then retires frames whose test passed (their state
+// stays at iteration l-1).  One final test pass covers the last iteration.
+//
+// Data layout (frame interleaved): B frames form G = ceil(B / W) groups of W
+// frames; every per-item float array is [G][items][W], so one item's W
+// frames are contiguous (W = 64: one 256-byte row per item, one lane per
+// frame).  Per-item bit words (syndrome, leaf decisions, flags) hold the W
+// frames of a group in one uint64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "met_internal.h"
+
+namespace met {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr float kLlrMax = 30.0f;
+
+enum : int32_t {
+  F_FIRST = 1,     // iteration 1: P = L, c2v = 0
+  F_TEST = 2,      // evaluate the syndrome test of the previous iteration
+  F_POST = 4,      // store leaf posteriors
+  F_WEIGHTED = 8,  // scale c2v by a per-(edge type, iteration) weight
+};
+
+// phi(x) = ln coth(x/2) = -ln tanh(x/2) for x >= 0; phi(0) = inf, phi(inf) = 0.
+// Two pieces, both evaluated (a select, no divergence):
+//  x < 1:  ln(2/x) + z p(z), z = x^2 -- p approximates (ln coth(x/2) - ln(2/x))/x^2
+//  x >= 1: 2u (1 + v q(v)), u = e^-x, v = u^2 -- q approximates (artanh(u)/u - 1)/u^2
+// The four coefficients of p and of q are least-squares fits to those smooth
+// functions on [0, 1] and [0, e^-2] (relative error of phi below 5e-8).
+constexpr float kP0 = 0.08333319759866183f, kP1 = -0.004859869600170282f;
+constexpr float kP2 = 0.00033799735484266977f, kP3 = -2.1679784689824217e-05f;
+constexpr float kQ0 = 0.3333317118955837f, kQ1 = 0.2001411345623163f;
+constexpr float kQ2 = 0.1393155479518919f, kQ3 = 0.1439900625146655f;
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float phi(float x) {
+  const float z = x * x;
+  const float ps = z * fmaf(z, fmaf(z, fmaf(z, kP3, kP2), kP1), kP0);
+  const float lo = fmaf(-kLn2, __builtin_amdgcn_logf(x), kLn2) + ps;
+  const float u = __builtin_amdgcn_exp2f(-x * kLog2e);
+  const float v = u * u;
+  const float hi = 2.0f * u * fmaf(v, fmaf(v, fmaf(v, fmaf(v, kQ3, kQ2), kQ1), kQ0), 1.0f);
+  return x < 1.0f ? lo : hi;
+}
+
+__device__ __forceinline__ float clamp_llr(float x) { return fminf(fmaxf(x, -kLlrMax), kLlrMax); }
+
+__device__ __forceinline__ uint32_t sign_bit(float x) { return __float_as_uint(x) >> 31; }
+
+template <int W>
+__device__ __forceinline__ uint64_t wmask() {
+  return W == 64 ? ~0ull : ((1ull << W) - 1ull);
+}
+
+// OR of the W-bit chunks of a wave ballot (lane = item * W + frame).
+template <int W>
+__device__ __forceinline__ uint64_t fold(uint64_t b) {
+  uint64_t r = 0;
+#pragma unroll
+  for (int q = 0; q < 64 / W; ++q) r |= (b >> (q * W)) & wmask<W>();
+  return r;
+}
+
+struct ClassArgs {
+  int32_t shape, n_msg, n_leaf, block_begin;
+  int64_t first_check, n_checks, first_msg, first_leaf;
+};
+
+struct CheckParams {
+  const int32_t *edge_msgvn;
+  const int8_t *edge_type;
+  const int8_t *leaf_type;
+  const int32_t *chk_msg_ptr;
+  const int32_t *chk_leaf_ptr;
+  int64_t M, N2, E12, EL;
+  const float *Pin;      // [G][N2][W]  P^{l-1} (L when F_FIRST)
+  float *c2v;            // [G][E12][W] read (unless F_FIRST) and written in place
+  const float *Lphi;     // [G][EL][W]  sign(L) * phi(|L|) of leaf VNs
+  const float *Lraw;     // [G][EL][W]  leaf LLRs (F_POST / F_WEIGHTED)
+  float *P1;             // [G][EL][W]  leaf posteriors of this iteration (F_POST)
+  const uint64_t *synw;  // [G][M]
+  const uint64_t *B1in;  // [G][EL] leaf decisions of iteration l-1 (F_TEST)
+  uint64_t *B1out;       // [G][EL] leaf decisions of iteration l
+  uint64_t *unsat;       // [G] frames with an unsatisfied check (F_TEST)
+  uint64_t *unsat_clear; // [G] buffer to zero for iteration l+1's test
+  const uint64_t *active;
+  const float *weights;  // [T][wstride]
+  int32_t wstride, it, flags, items_per_wave, n_classes, G;
+  ClassArgs cls[kMaxClasses];
+};
+
+// Decision of a leaf VN after the check update: c = 1 iff L + c2v < 0, with
+// c2v = sgn * phi(S) and |L| = phi(A).  Since phi decreases, |c2v| > |L| iff
+// S < A; a tie (P = 0) decides 0.
+__device__ __forceinline__ uint32_t leaf_bit(uint32_t neg_l, uint32_t neg_c, float S, float A) {
+  if (neg_l == neg_c) return neg_l & (uint32_t)!(isinf(A) && isinf(S));
+  if (S < A) return neg_c;
+  if (S > A) return neg_l;
+  return 0u;
+}
+
+struct Lane {
+  int g, w, q;
+  uint64_t act;       // active frames of the group
+  bool lane_act;      // this lane's frame is active
+};
+
+// One check with a compile-time shape: NM message edges, NL leaf edges.
+template <int W, int NM, int NL>
+__device__ __forceinline__ void check_fixed(const CheckParams &p, const Lane &L, bool valid, int64_t j,
+                                            int64_t m0, int64_t l0, uint32_t &bad) {
+  constexpr int D = NM + NL;
+  const int g = L.g, w = L.w;
+  const uint32_t s = (uint32_t)(p.synw[(int64_t)g * p.M + j] >> w) & 1u;
+  const bool first = p.flags & F_FIRST, test = p.flags & F_TEST;
+  float A[D];
+  uint32_t neg = 0, parity = s;
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    const int64_t e = m0 + k;
+    const int32_t vi = p.edge_msgvn[e];
+    const float pv = p.Pin[((int64_t)g * p.N2 + vi) * W + w];
+    const float c = first ? 0.0f : p.c2v[((int64_t)g * p.E12 + e) * W + w];
+    parity ^= (uint32_t)(pv < 0.0f);
+    const float x = clamp_llr(pv - c);
+    A[k] = phi(fabsf(x));
+    neg |= sign_bit(x) << k;
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int64_t le = l0 + k;
+    const float f = p.Lphi[((int64_t)g * p.EL + le) * W + w];
+    A[NM + k] = fabsf(f);
+    neg |= sign_bit(f) << (NM + k);
+    if (test) parity ^= (uint32_t)(p.B1in[(int64_t)g * p.EL + le] >> w) & 1u;
+  }
+  if (test) bad |= parity & (uint32_t)(valid && L.lane_act);
+  const uint32_t tot = (__popc(neg) & 1u) ^ s;
+  // leave-one-out sums: S_k = prefix_k + suffix_k
+  float pre[D], suf[D];
+  pre[0] = 0.0f;
+#pragma unroll
+  for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + A[k - 1];
+  suf[D - 1] = 0.0f;
+#pragma unroll
+  for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] + A[k + 1];
+  const bool weighted = p.flags & F_WEIGHTED;
+  const bool store = valid && L.lane_act;
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    const float mag = phi(pre[k] + suf[k]);
+    float out = ((tot ^ (neg >> k)) & 1u) ? -mag : mag;
+    if (weighted) out *= p.weights[(int64_t)p.edge_type[m0 + k] * p.wstride + (p.it - 1)];
+    if (store) p.c2v[((int64_t)g * p.E12 + m0 + k) * W + w] = out;
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int64_t le = l0 + k;
+    const float S = pre[NM + k] + suf[NM + k];
+    const uint32_t neg_l = (neg >> (NM + k)) & 1u;
+    const uint32_t neg_c = (tot ^ neg_l) & 1u;
+    uint32_t bit;
+    float wt = 1.0f;
+    if (weighted) wt = p.weights[(int64_t)p.leaf_type[le] * p.wstride + (p.it - 1)];
+    if (wt == 1.0f) {
+      bit = leaf_bit(neg_l, neg_c, S, A[NM + k]);
+    } else {
+      const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
+      const float mag = phi(S);
+      bit = (uint32_t)(lr + wt * (neg_c ? -mag : mag) < 0.0f);
+    }
+    if (p.flags & F_POST) {
+      const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
+      const float mag = phi(S);
+      if (store) p.P1[((int64_t)g * p.EL + le) * W + w] = lr + wt * (neg_c ? -mag : mag);
+    }
+    const uint64_t ball = __ballot((int)(bit & (uint32_t)valid));
+    if (L.w == 0 && valid) {
+      const uint64_t chunk = (ball >> (L.q * W)) & wmask<W>();
+      uint64_t *dst = p.B1out + (int64_t)g * p.EL + le;
+      *dst = (L.act == wmask<W>()) ? chunk : ((*dst & ~L.act) | (chunk & L.act));
+    }
+  }
+}
+
+// One check with run-time degrees (total degree <= MET_MAX_CHECK_DEGREE).
+template <int W>
+__device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &L, bool valid, int64_t j,
+                                              uint32_t &bad) {
+  constexpr int D = MET_MAX_CHECK_DEGREE;
+  const int g = L.g, w = L.w;
+  const int64_t m0 = p.chk_msg_ptr[j], l0 = p.chk_leaf_ptr[j];
+  const int nm = p.chk_msg_ptr[j + 1] - (int32_t)m0;
+  const int nl = p.chk_leaf_ptr[j + 1] - (int32_t)l0;
+  const uint32_t s = (uint32_t)(p.synw[(int64_t)g * p.M + j] >> w) & 1u;
+  const bool first = p.flags & F_FIRST, test = p.flags & F_TEST;
+  float A[D];
+  uint32_t neg = 0, parity = s;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    A[k] = 0.0f;  // phi-domain identity: an absent input adds nothing
+    if (k < nm) {
+      const int64_t e = m0 + k;
+      const float pv = p.Pin[((int64_t)g * p.N2 + p.edge_msgvn[e]) * W + w];
+      const float c = first ? 0.0f : p.c2v[((int64_t)g * p.E12 + e) * W + w];
+      parity ^= (uint32_t)(pv < 0.0f);
+      const float x = clamp_llr(pv - c);
+      A[k] = phi(fabsf(x));
+      neg |= sign_bit(x) << k;
+    } else if (k < nm + nl) {
+      const int64_t le = l0 + (k - nm);
+      const float f = p.Lphi[((int64_t)g * p.EL + le) * W + w];
+      A[k] = fabsf(f);
+      neg |= sign_bit(f) << k;
+      if (test) parity ^= (uint32_t)(p.B1in[(int64_t)g * p.EL + le] >> w) & 1u;
+    }
+  }
+  if (test) bad |= parity & (uint32_t)(valid && L.lane_act);
+  const uint32_t tot = (__popc(neg) & 1u) ^ s;
+  float pre[D], suf[D];
+  pre[0] = 0.0f;
+#pragma unroll
+  for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + A[k - 1];
+  suf[D - 1] = 0.0f;
+#pragma unroll
+  for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] + A[k + 1];
+  const bool weighted = p.flags & F_WEIGHTED;
+  const bool store = valid && L.lane_act;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    if (k < nm) {
+      const float mag = phi(pre[k] + suf[k]);
+      float out = ((tot ^ (neg >> k)) & 1u) ? -mag : mag;
+      if (weighted) out *= p.weights[(int64_t)p.edge_type[m0 + k] * p.wstride + (p.it - 1)];
+      if (store) p.c2v[((int64_t)g * p.E12 + m0 + k) * W + w] = out;
+    }
+  }
+  // Leaf decisions: ballots must be executed by every lane of the wave, so the
+  // loop runs to the wave-wide maximum leaf count.
+  int nl_max = nl;
+  for (int off = 32; off >= 1; off >>= 1) nl_max = max(nl_max, __shfl_xor(nl_max, off));
+  for (int k = 0; k < nl_max; ++k) {
+    const bool has = valid && k < nl;
+    const int kk = nm + k;
+    const int64_t le = l0 + (has ? k : 0);
+    float S = 0.0f, Aleaf = 0.0f;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+      if (r == kk) {
+        S = pre[r] + suf[r];
+        Aleaf = A[r];
+      }
+    const uint32_t neg_l = (neg >> (kk & 31)) & 1u;
+    const uint32_t neg_c = (tot ^ neg_l) & 1u;
+    uint32_t bit = 0;
+    float wt = 1.0f;
+    if (has) {
+      if (weighted) wt = p.weights[(int64_t)p.leaf_type[le] * p.wstride + (p.it - 1)];
+      if (wt == 1.0f) {
+        bit = leaf_bit(neg_l, neg_c, S, Aleaf);
+      } else {
+        const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
+        const float mag = phi(S);
+        bit = (uint32_t)(lr + wt * (neg_c ? -mag : mag) < 0.0f);
+      }
+      if ((p.flags & F_POST) && store) {
+        const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
+        const float mag = phi(S);
+        p.P1[((int64_t)g * p.EL + le) * W + w] = lr + wt * (neg_c ? -mag : mag);
+      }
+    }
+    const uint64_t ball = __ballot((int)bit);
+    if (L.w == 0 && has) {
+      const uint64_t chunk = (ball >> (L.q * W)) & wmask<W>();
+      uint64_t *dst = p.B1out + (int64_t)g * p.EL + le;
+      *dst = (L.act == wmask<W>()) ? chunk : ((*dst & ~L.act) | (chunk & L.act));
+    }
+  }
+}
+
+template <int W, int NM, int NL>
+__device__ __forceinline__ void run_fixed(const CheckParams &p, const ClassArgs &c, const Lane &L, int64_t item0,
+                                          int wv, uint32_t &bad) {
+  constexpr int IPWAVE = 64 / W;  // items per wave step
+  for (int k = 0; k < p.items_per_wave; ++k) {
+    const int64_t item = item0 + ((int64_t)k * kWavesPerBlock + wv) * IPWAVE + L.q;
+    const bool valid = item < c.n_checks;
+    const int64_t it = valid ? item : 0;
+    if (W == 64 && !valid) break;
+    check_fixed<W, NM, NL>(p, L, valid, c.first_check + it, c.first_msg + it * NM, c.first_leaf + it * NL, bad);
+  }
+}
+
+// Check update of all checks of the classes in p.cls; the GENERIC instance
+// handles only run-time-degree classes, the other one only compiled shapes
+// (so the common shapes keep a small register footprint).
+template <int W, bool GENERIC>
+__global__ __launch_bounds__(kBlock) void k_check(const CheckParams p) {
+  const int g = blockIdx.y;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && p.unsat_clear)
+    for (int gg = threadIdx.x; gg < p.G; gg += kBlock) p.unsat_clear[gg] = 0ull;
+  const uint64_t act = p.active[g];
+  if (act == 0ull) return;
+  int ci = 0;
+  while (ci + 1 < p.n_classes && (int)blockIdx.x >= p.cls[ci + 1].block_begin) ++ci;
+  const ClassArgs &c = p.cls[ci];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  Lane L;
+  L.g = g;
+  L.w = lane % W;
+  L.q = lane / W;
+  L.act = act;
+  L.lane_act = (act >> L.w) & 1ull;
+  const int64_t per_block = (int64_t)p.items_per_wave * kWavesPerBlock * (64 / W);
+  const int64_t item0 = (int64_t)(blockIdx.x - c.block_begin) * per_block;
+  uint32_t bad = 0;
+  switch (c.shape) {
+    case 0: run_fixed<W, 3, 1>(p, c, L, item0, wv, bad); break;
+    case 1: run_fixed<W, 2, 1>(p, c, L, item0, wv, bad); break;
+    case 2: run_fixed<W, 4, 1>(p, c, L, item0, wv, bad); break;
+    case 3: run_fixed<W, 12, 0>(p, c, L, item0, wv, bad); break;
+    case 4: run_fixed<W, 11, 0>(p, c, L, item0, wv, bad); break;
+    case 5: run_fixed<W, 13, 0>(p, c, L, item0, wv, bad); break;
+    case 6: run_fixed<W, 6, 0>(p, c, L, item0, wv, bad); break;
+    case 7: run_fixed<W, 5, 0>(p, c, L, item0, wv, bad); break;
+    case 8: run_fixed<W, 7, 0>(p, c, L, item0, wv, bad); break;
+    default: {
+      if (GENERIC) {
+        constexpr int IPWAVE = 64 / W;
+        for (int k = 0; k < p.items_per_wave; ++k) {
+          const int64_t item = item0 + ((int64_t)k * kWavesPerBlock + wv) * IPWAVE + L.q;
+          const bool valid = item < c.n_checks;
+          if (W == 64 && !valid) break;
+          check_generic<W>(p, L, valid, c.first_check + (valid ? item : 0), bad);
+        }
+      }
+    }
+  }
+  if (p.flags & F_TEST) {
+    const uint64_t f = fold<W>(__ballot((int)bad));
+    if (lane == 0 && f) {
+      uint64_t *dst = p.unsat + g;
+      const uint64_t seen = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (f & ~seen) __hip_atomic_fetch_or(dst, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// Syndrome test only (after the last iteration): parity of the hard decisions
+// of P^l (message VNs) and of the stored leaf decisions against s.
+struct TestParams {
+  const int32_t *edge_msgvn, *chk_msg_ptr, *chk_leaf_ptr;
+  int64_t M, N2, E12, EL;
+  const float *P;
+  const uint64_t *synw, *B1, *active;
+  uint64_t *unsat;
+};
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_test(const TestParams p) {
+  const int g = blockIdx.y;
+  const uint64_t act = p.active[g];
+  if (act == 0ull) return;
+  const int lane = threadIdx.x & 63, w = lane % W, q = lane / W;
+  const int64_t j = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * (64 / W) + q;
+  uint32_t bad = 0;
+  if (j < p.M) {
+    uint32_t parity = (uint32_t)(p.synw[(int64_t)g * p.M + j] >> w) & 1u;
+    for (int32_t e = p.chk_msg_ptr[j]; e < p.chk_msg_ptr[j + 1]; ++e)
+      parity ^= (uint32_t)(p.P[((int64_t)g * p.N2 + p.edge_msgvn[e]) * W + w] < 0.0f);
+    for (int32_t e = p.chk_leaf_ptr[j]; e < p.chk_leaf_ptr[j + 1]; ++e)
+      parity ^= (uint32_t)(p.B1[(int64_t)g * p.EL + e] >> w) & 1u;
+    bad = parity & (uint32_t)((act >> w) & 1ull);
+  }
+  const uint64_t f = fold<W>(__ballot((int)bad));
+  if (lane == 0 && f) {
+    uint64_t *dst = p.unsat + g;
+    const uint64_t seen = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (f & ~seen) __hip_atomic_fetch_or(dst, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+struct VarParams {
+  const int32_t *vn_ptr, *vn_edges;
+  int64_t N2, E12;
+  const float *L2;       // [G][N2][W]
+  const float *c2v;      // [G][E12][W]
+  float *P;              // [G][N2][W]
+  uint64_t *active;      // [G]
+  const uint64_t *unsat; // [G] test result of iteration it-1 (retire mode)
+  int32_t *iters;
+  uint8_t *converged;
+  int32_t it, retire, items_per_wave, G, B;
+};
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
+  const int g = blockIdx.y;
+  uint64_t act = p.active[g];
+  if (p.retire) {
+    // Frames whose test of iteration it-1 passed stop here; their P stays at
+    // iteration it-1.  Block (0,0) records the outcome for every group.
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+      for (int gg = threadIdx.x; gg < p.G; gg += kBlock) {
+        const uint64_t a = p.active[gg], u = p.unsat[gg];
+        const uint64_t done = a & ~u;
+        if (done) {
+          for (int w = 0; w < W; ++w)
+            if ((done >> w) & 1ull) {
+              const int f = gg * W + w;
+              p.iters[f] = p.it - 1;
+              p.converged[f] = 1;
+            }
+          p.active[gg] = a & u;
+        }
+      }
+    }
+    act &= p.unsat[g];
+  }
+  if (act == 0ull) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, w = lane % W, q = lane / W;
+  const bool lane_act = (act >> w) & 1ull;
+  const int64_t per_block = (int64_t)p.items_per_wave * kWavesPerBlock * (64 / W);
+  const int64_t base = (int64_t)blockIdx.x * per_block;
+  for (int k = 0; k < p.items_per_wave; ++k) {
+    const int64_t i = base + ((int64_t)k * kWavesPerBlock + wv) * (64 / W) + q;
+    if (i >= p.N2) break;
+    const int32_t e0 = p.vn_ptr[i], e1 = p.vn_ptr[i + 1];
+    float P = p.L2[((int64_t)g * p.N2 + i) * W + w];
+    const float *c2v = p.c2v + (int64_t)g * p.E12 * W + w;
+    int32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      const float a0 = c2v[(int64_t)p.vn_edges[e] * W];
+      const float a1 = c2v[(int64_t)p.vn_edges[e + 1] * W];
+      const float a2 = c2v[(int64_t)p.vn_edges[e + 2] * W];
+      const float a3 = c2v[(int64_t)p.vn_edges[e + 3] * W];
+      P += a0;
+      P += a1;
+      P += a2;
+      P += a3;
+    }
+    for (; e < e1; ++e) P += c2v[(int64_t)p.vn_edges[e] * W];
+    if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Set-up and output kernels
+
+struct InitParams {
+  const float *llr;       // [B][N]
+  const uint8_t *syn;     // [B][M]
+  const int32_t *msg_vn_user, *leaf_vn;
+  int64_t N, M, N2, EL;
+  int32_t B, G;
+  float *Lt;              // [G][N][W] staging
+  float *L2, *Lphi, *Lraw;
+  uint64_t *synw, *active, *unsat;
+  int32_t *iters;
+  uint8_t *converged;
+};
+
+// llr [B][N] -> Lt [G][N][W]; lanes run along N so every row read is coalesced.
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_transpose(const InitParams p) {
+  const int g = blockIdx.y;
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= p.N) return;
+  float *dst = p.Lt + ((int64_t)g * p.N + v) * W;
+#pragma unroll 8
+  for (int w = 0; w < W; ++w) {
+    const int f = g * W + w;
+    dst[w] = f < p.B ? p.llr[(int64_t)f * p.N + v] : 0.0f;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_init_items(const InitParams p) {
+  const int g = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;  // item * W + w
+  const int64_t item = idx / W;
+  const int w = (int)(idx % W);
+  if (item < p.N2) {
+    p.L2[((int64_t)g * p.N2 + item) * W + w] = p.Lt[((int64_t)g * p.N + p.msg_vn_user[item]) * W + w];
+  } else if (item < p.N2 + p.EL) {
+    const int64_t le = item - p.N2;
+    const float l = p.Lt[((int64_t)g * p.N + p.leaf_vn[le]) * W + w];
+    p.Lphi[((int64_t)g * p.EL + le) * W + w] = copysignf(phi(fabsf(l)), l);
+    if (p.Lraw) p.Lraw[((int64_t)g * p.EL + le) * W + w] = l;
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_pack_syndrome(const InitParams p) {
+  const int g = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j < p.M) {
+    uint64_t word = 0;
+    for (int w = 0; w < W; ++w) {
+      const int f = g * W + w;
+      if (f < p.B) word |= (uint64_t)(p.syn[(int64_t)f * p.M + j] & 1u) << w;
+    }
+    p.synw[(int64_t)g * p.M + j] = word;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int valid = min(W, p.B - g * W);
+    p.active[g] = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+    p.unsat[g] = 0ull;
+    p.unsat[p.G + g] = 0ull;
+    for (int w = 0; w < valid; ++w) {
+      p.iters[g * W + w] = 0;
+      p.converged[g * W + w] = 0;
+    }
+  }
+}
+
+struct FinalParams {
+  const int32_t *vn_slot;
+  int64_t N, N2, EL;
+  int32_t B, max_iter;
+  const float *P;               // [G][N2][W]
+  const float *P1a, *P1b;       // leaf posteriors of even / odd iterations (or NULL)
+  const uint64_t *B1a, *B1b;    // leaf decisions of even / odd iterations
+  const uint64_t *active, *unsat_last;
+  int32_t *iters;
+  uint8_t *converged;
+  uint8_t *bits;
+  float *posterior;
+  int32_t G;
+};
+
+// Outcome of frames still running after the last iteration.
+template <int W>
+__global__ void k_final_status(const FinalParams p) {
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < p.B; f += gridDim.x * blockDim.x) {
+    const int g = f / W, w = f % W;
+    if ((p.active[g] >> w) & 1ull) {
+      p.iters[f] = p.max_iter;
+      p.converged[f] = (uint8_t)!((p.unsat_last[g] >> w) & 1ull);
+    }
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_finalize(const FinalParams p) {
+  const int f = blockIdx.y;
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= p.N) return;
+  const int g = f / W, w = f % W;
+  const int32_t slot = p.vn_slot[v];
+  const bool odd = p.iters[f] & 1;
+  uint8_t bit;
+  float post = 0.0f;
+  if (slot >= 0) {
+    post = p.P[((int64_t)g * p.N2 + slot) * W + w];
+    bit = post < 0.0f;
+  } else {
+    const int64_t le = -(int64_t)slot - 1;
+    bit = (uint8_t)(((odd ? p.B1b : p.B1a)[(int64_t)g * p.EL + le] >> w) & 1ull);
+    if (p.posterior) post = (odd ? p.P1b : p.P1a)[((int64_t)g * p.EL + le) * W + w];
+  }
+  p.bits[(int64_t)f * p.N + v] = bit;
+  if (p.posterior) p.posterior[(int64_t)f * p.N + v] = post;
+}
+
+__global__ __launch_bounds__(kBlock) void k_syndrome(const int32_t *all_vn, const int32_t *all_ptr, int64_t N,
+                                                     int64_t M, const uint8_t *bits, uint8_t *syn) {
+  const int f = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= M) return;
+  uint32_t s = 0;
+  for (int32_t e = all_ptr[j]; e < all_ptr[j + 1]; ++e) s ^= bits[(int64_t)f * N + all_vn[e]] & 1u;
+  syn[(int64_t)f * M + j] = (uint8_t)s;
+}
+
+// ----------------------------------------------------------------------------
+// Host orchestration
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+  int W = 64, G = 1;
+  size_t off_c2v = 0, off_P = 0, off_L2 = 0, off_Lphi = 0, off_Lraw = 0, off_P1 = 0, off_synw = 0, off_B1 = 0,
+         off_unsat = 0, off_active = 0, total = 0;
+  bool lraw = false, p1 = false;
+};
+
+int choose_interleave(int B) {
+  int W = 1;
+  while (W < B && W < 64) W <<= 1;
+  return W;
+}
+
+Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
+  Plan pl;
+  pl.W = W;
+  pl.G = (B + W - 1) / W;
+  const size_t GW = (size_t)pl.G * W;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  // c2v also serves as the staging area of the input transpose.
+  pl.off_c2v = take(std::max<size_t>(GW * c->E12, GW * c->N) * sizeof(float));
+  pl.off_P = take(GW * c->N2 * sizeof(float));
+  pl.off_L2 = take(GW * c->N2 * sizeof(float));
+  pl.off_Lphi = take(GW * c->EL * sizeof(float));
+  pl.lraw = post || weighted;
+  pl.p1 = post;
+  pl.off_Lraw = pl.lraw ? take(GW * c->EL * sizeof(float)) : 0;
+  pl.off_P1 = pl.p1 ? take(2 * GW * c->EL * sizeof(float)) : 0;
+  pl.off_synw = take((size_t)pl.G * c->M * sizeof(uint64_t));
+  pl.off_B1 = take(2 * (size_t)pl.G * c->EL * sizeof(uint64_t));
+  pl.off_unsat = take(2 * (size_t)pl.G * sizeof(uint64_t));
+  pl.off_active = take((size_t)pl.G * sizeof(uint64_t));
+  pl.total = o;
+  return pl;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(MET_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct Decoder {
+  const met_code *c;
+  const DeviceCode *d;
+  Plan pl;
+  char *ws;
+  hipStream_t st;
+  int B;
+  int cn_ipw = 2, vn_ipw = 1;
+
+  template <typename T>
+  T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+
+  template <int W>
+  int run(const float *llr, const uint8_t *syn, int max_iter, uint32_t flags, uint8_t *bits, int32_t *iters,
+          uint8_t *conv, float *post, const float *weights, int32_t wstride) {
+    const int G = pl.G;
+    float *c2v = at<float>(pl.off_c2v), *P = at<float>(pl.off_P), *L2 = at<float>(pl.off_L2);
+    float *Lphi = at<float>(pl.off_Lphi);
+    float *Lraw = pl.lraw ? at<float>(pl.off_Lraw) : nullptr;
+    float *P1 = pl.p1 ? at<float>(pl.off_P1) : nullptr;
+    uint64_t *synw = at<uint64_t>(pl.off_synw), *B1 = at<uint64_t>(pl.off_B1);
+    uint64_t *unsat = at<uint64_t>(pl.off_unsat), *active = at<uint64_t>(pl.off_active);
+    const size_t leaf_words = (size_t)G * c->EL;
+    const size_t leaf_floats = (size_t)G * c->EL * W;
+
+    InitParams ip{};
+    ip.llr = llr;
+    ip.syn = syn;
+    ip.msg_vn_user = d->msg_vn_user;
+    ip.leaf_vn = d->leaf_vn;
+    ip.N = c->N;
+    ip.M = c->M;
+    ip.N2 = c->N2;
+    ip.EL = c->EL;
+    ip.B = B;
+    ip.G = G;
+    ip.Lt = c2v;
+    ip.L2 = L2;
+    ip.Lphi = Lphi;
+    ip.Lraw = Lraw;
+    ip.synw = synw;
+    ip.active = active;
+    ip.unsat = unsat;
+    ip.iters = iters;
+    ip.converged = conv;
+    hipLaunchKernelGGL(k_transpose<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st, ip);
+    {
+      const int64_t n = (c->N2 + c->EL) * W;
+      if (n > 0)
+        hipLaunchKernelGGL(k_init_items<W>, dim3((unsigned)((n + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st, ip);
+    }
+    hipLaunchKernelGGL(k_pack_syndrome<W>, dim3((unsigned)std::max<int64_t>(1, (c->M + kBlock - 1) / kBlock), G),
+                       dim3(kBlock), 0, st, ip);
+
+    CheckParams cp{};
+    cp.edge_msgvn = d->edge_msgvn;
+    cp.edge_type = d->edge_type;
+    cp.leaf_type = d->leaf_type;
+    cp.chk_msg_ptr = d->chk_msg_ptr;
+    cp.chk_leaf_ptr = d->chk_leaf_ptr;
+    cp.M = c->M;
+    cp.N2 = c->N2;
+    cp.E12 = c->E12;
+    cp.EL = c->EL;
+    cp.c2v = c2v;
+    cp.Lphi = Lphi;
+    cp.Lraw = Lraw;
+    cp.synw = synw;
+    cp.active = active;
+    cp.weights = weights;
+    cp.wstride = wstride;
+    cp.items_per_wave = cn_ipw;
+    cp.G = G;
+    // Fixed-shape classes go to one launch, run-time-degree classes to another.
+    CheckParams gp = cp;
+    int cn_blocks = 0, gen_blocks = 0;
+    cp.n_classes = 0;
+    gp.n_classes = 0;
+    const int64_t per_block = (int64_t)cn_ipw * kWavesPerBlock * (64 / W);
+    for (const CheckClass &cc : c->classes) {
+      const bool gen = cc.shape == kShapeGeneric;
+      CheckParams &dst = gen ? gp : cp;
+      int &blocks = gen ? gen_blocks : cn_blocks;
+      ClassArgs &a = dst.cls[dst.n_classes++];
+      a.shape = cc.shape;
+      a.n_msg = cc.n_msg;
+      a.n_leaf = cc.n_leaf;
+      a.first_check = cc.first_check;
+      a.n_checks = cc.n_checks;
+      a.first_msg = cc.first_msg;
+      a.first_leaf = cc.first_leaf;
+      a.block_begin = blocks;
+      blocks += (int)((cc.n_checks + per_block - 1) / per_block);
+    }
+    VarParams vp{};
+    vp.vn_ptr = d->vn_ptr;
+    vp.vn_edges = d->vn_edges;
+    vp.N2 = c->N2;
+    vp.E12 = c->E12;
+    vp.L2 = L2;
+    vp.c2v = c2v;
+    vp.P = P;
+    vp.active = active;
+    vp.iters = iters;
+    vp.converged = conv;
+    vp.items_per_wave = vn_ipw;
+    vp.G = G;
+    vp.B = B;
+    const int64_t vn_per_block = (int64_t)vn_ipw * kWavesPerBlock * (64 / W);
+    const unsigned vn_blocks = (unsigned)((c->N2 + vn_per_block - 1) / vn_per_block);
+    const bool early = !(flags & MET_FIXED_ITERS);
+    const int base_flags = (post ? F_POST : 0) | (weights ? F_WEIGHTED : 0);
+
+    for (int it = 1; it <= max_iter; ++it) {
+      cp.it = it;
+      cp.flags = base_flags | (it == 1 ? F_FIRST : 0) | (early && it >= 2 ? F_TEST : 0);
+      cp.Pin = it == 1 ? L2 : P;
+      cp.B1in = B1 + (size_t)((it - 1) & 1) * leaf_words;
+      cp.B1out = B1 + (size_t)(it & 1) * leaf_words;
+      cp.P1 = P1 ? P1 + (size_t)(it & 1) * leaf_floats : nullptr;
+      cp.unsat = unsat + (size_t)((it - 1) & 1) * G;
+      cp.unsat_clear = unsat + (size_t)(it & 1) * G;
+      if (cn_blocks > 0) hipLaunchKernelGGL((k_check<W, false>), dim3(cn_blocks, G), dim3(kBlock), 0, st, cp);
+      if (gen_blocks > 0) {
+        gp.it = cp.it;
+        gp.flags = cp.flags;
+        gp.Pin = cp.Pin;
+        gp.B1in = cp.B1in;
+        gp.B1out = cp.B1out;
+        gp.P1 = cp.P1;
+        gp.unsat = cp.unsat;
+        gp.unsat_clear = cn_blocks > 0 ? nullptr : cp.unsat_clear;
+        hipLaunchKernelGGL((k_check<W, true>), dim3(gen_blocks, G), dim3(kBlock), 0, st, gp);
+      }
+      vp.it = it;
+      vp.retire = early && it >= 2;
+      vp.unsat = unsat + (size_t)((it - 1) & 1) * G;
+      if (vn_blocks > 0) hipLaunchKernelGGL(k_variable<W>, dim3(vn_blocks, G), dim3(kBlock), 0, st, vp);
+    }
+    TestParams tp{};
+    tp.edge_msgvn = d->edge_msgvn;
+    tp.chk_msg_ptr = d->chk_msg_ptr;
+    tp.chk_leaf_ptr = d->chk_leaf_ptr;
+    tp.M = c->M;
+    tp.N2 = c->N2;
+    tp.E12 = c->E12;
+    tp.EL = c->EL;
+    tp.P = P;
+    tp.synw = synw;
+    tp.B1 = B1 + (size_t)(max_iter & 1) * leaf_words;
+    tp.active = active;
+    tp.unsat = unsat + (size_t)(max_iter & 1) * G;
+    {
+      const int64_t per = (int64_t)kWavesPerBlock * (64 / W);
+      hipLaunchKernelGGL(k_test<W>, dim3((unsigned)((c->M + per - 1) / per), G), dim3(kBlock), 0, st, tp);
+    }
+    FinalParams fp{};
+    fp.vn_slot = d->vn_slot;
+    fp.N = c->N;
+    fp.N2 = c->N2;
+    fp.EL = c->EL;
+    fp.B = B;
+    fp.max_iter = max_iter;
+    fp.P = P;
+    fp.P1a = P1;
+    fp.P1b = P1 ? P1 + leaf_floats : nullptr;
+    fp.B1a = B1;
+    fp.B1b = B1 + leaf_words;
+    fp.active = active;
+    fp.unsat_last = unsat + (size_t)(max_iter & 1) * G;
+    fp.iters = iters;
+    fp.converged = conv;
+    fp.bits = bits;
+    fp.posterior = post;
+    fp.G = G;
+    hipLaunchKernelGGL(k_final_status<W>, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fp);
+    hipLaunchKernelGGL(k_finalize<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), B), dim3(kBlock), 0, st, fp);
+    HIP_TRY(hipGetLastError());
+    return MET_OK;
+  }
+};
+
+}  // namespace
+
+int device_code(const met_code *cc, const DeviceCode **out) {
+  met_code *c = const_cast<met_code *>(cc);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MET_EINVAL, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(c->mu);
+  DeviceCode &d = c->dev[dev];
+  if (d.ready) {
+    *out = &d;
+    return MET_OK;
+  }
+  struct Part {
+    const void *src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Part> parts = {
+      {c->edge_msgvn.data(), c->edge_msgvn.size() * 4, 0},   {c->edge_type_msg.data(), c->edge_type_msg.size(), 0},
+      {c->vn_ptr.data(), c->vn_ptr.size() * 4, 0},           {c->vn_edges.data(), c->vn_edges.size() * 4, 0},
+      {c->leaf_vn_user.data(), c->leaf_vn_user.size() * 4, 0}, {c->leaf_type.data(), c->leaf_type.size(), 0},
+      {c->msg_vn_user.data(), c->msg_vn_user.size() * 4, 0}, {c->vn_slot.data(), c->vn_slot.size() * 4, 0},
+      {c->chk_msg_ptr.data(), c->chk_msg_ptr.size() * 4, 0}, {c->chk_leaf_ptr.data(), c->chk_leaf_ptr.size() * 4, 0},
+      {c->vn.data(), c->vn.size() * 4, 0},                   {c->chk_ptr.data(), c->chk_ptr.size() * 4, 0},
+  };
+  size_t total = 0;
+  for (Part &p : parts) {
+    p.off = total;
+    total += align256(std::max<size_t>(p.bytes, 4));
+  }
+  void *base = nullptr;
+  hipError_t e = hipMalloc(&base, total);
+  if (e != hipSuccess) return fail(MET_ENOMEM, "hipMalloc(%zu) for the adjacency: %s", total, hipGetErrorString(e));
+  for (const Part &p : parts) {
+    if (p.bytes == 0) continue;
+    e = hipMemcpy(static_cast<char *>(base) + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(base);
+      return fail(MET_EHIP, "hipMemcpy of the adjacency: %s", hipGetErrorString(e));
+    }
+  }
+  char *b = static_cast<char *>(base);
+  d.base = base;
+  d.bytes = total;
+  d.edge_msgvn = reinterpret_cast<const int32_t *>(b + parts[0].off);
+  d.edge_type = reinterpret_cast<const int8_t *>(b + parts[1].off);
+  d.vn_ptr = reinterpret_cast<const int32_t *>(b + parts[2].off);
+  d.vn_edges = reinterpret_cast<const int32_t *>(b + parts[3].off);
+  d.leaf_vn = reinterpret_cast<const int32_t *>(b + parts[4].off);
+  d.leaf_type = reinterpret_cast<const int8_t *>(b + parts[5].off);
+  d.msg_vn_user = reinterpret_cast<const int32_t *>(b + parts[6].off);
+  d.vn_slot = reinterpret_cast<const int32_t *>(b + parts[7].off);
+  d.chk_msg_ptr = reinterpret_cast<const int32_t *>(b + parts[8].off);
+  d.chk_leaf_ptr = reinterpret_cast<const int32_t *>(b + parts[9].off);
+  d.all_vn = reinterpret_cast<const int32_t *>(b + parts[10].off);
+  d.all_ptr = reinterpret_cast<const int32_t *>(b + parts[11].off);
+  d.ready = true;
+  *out = &d;
+  return MET_OK;
+}
+
+}  // namespace met
+
+using met::fail;
+
+extern "C" void met_code_free(met_code *c) {
+  if (!c) return;
+  int cur = -1;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (int k = 0; k < met::kMaxDevices; ++k) {
+    if (c->dev[k].ready) {
+      if (hipSetDevice(k) == hipSuccess) (void)hipFree(c->dev[k].base);
+    }
+  }
+  if (have && cur >= 0) (void)hipSetDevice(cur);
+  delete c;
+}
+
+extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, uint8_t *syn, void *stream) {
+  met::clear_error();
+  if (!c || !bits || !syn) return fail(MET_EINVAL, "met_syndrome: NULL argument");
+  if (B < 1 || B > 65535) return fail(MET_EINVAL, "met_syndrome: B = %d outside 1..65535", B);
+  const met::DeviceCode *d = nullptr;
+  int rc = met::device_code(c, &d);
+  if (rc) return rc;
+  hipLaunchKernelGGL(met::k_syndrome, dim3((unsigned)((c->M + met::kBlock - 1) / met::kBlock), B),
+                     dim3(met::kBlock), 0, (hipStream_t)stream, d->all_vn, d->all_ptr, c->N, c->M, bits, syn);
+  HIP_TRY(hipGetLastError());
+  return MET_OK;
+}
+
+static int validate_decode(const met_code *c, int32_t B, uint32_t flags) {
+  if (!c) return fail(MET_EINVAL, "NULL code");
+  if (B < 1 || B > 65535) return fail(MET_EINVAL, "B = %d outside 1..65535", B);
+  if (flags & ~(uint32_t)MET_FIXED_ITERS) return fail(MET_EINVAL, "unknown flags 0x%x", flags);
+  return MET_OK;
+}
+
+extern "C" int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int32_t want_posterior,
+                                          size_t *bytes) {
+  met::clear_error();
+  int rc = validate_decode(c, B, flags);
+  if (rc) return rc;
+  if (!bytes) return fail(MET_EINVAL, "NULL bytes");
+  *bytes = met::make_plan(c, B, want_posterior != 0, false, met::choose_interleave(B)).total;
+  return MET_OK;
+}
+
+extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
+                          uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
+                          void *workspace, size_t ws_bytes, void *stream) {
+  met::clear_error();
+  int rc = validate_decode(c, B, flags);
+  if (rc) return rc;
+  if (!llr || !syn || !bits || !iters || !converged || !workspace) return fail(MET_EINVAL, "NULL buffer");
+  if (max_iter < 1 || max_iter > 1000000) return fail(MET_EINVAL, "max_iter = %d outside 1..10^6", max_iter);
+  if (((uintptr_t)llr & 3) || ((uintptr_t)posterior & 3) || ((uintptr_t)iters & 3))
+    return fail(MET_EINVAL, "misaligned float/int buffer");
+  if ((uintptr_t)workspace & 255) return fail(MET_EINVAL, "workspace must be 256-byte aligned");
+  const int W = met::choose_interleave(B);
+  const met::Plan pl = met::make_plan(c, B, posterior != nullptr, false, W);
+  if (ws_bytes < pl.total) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, pl.total);
+  const met::DeviceCode *d = nullptr;
+  rc = met::device_code(c, &d);
+  if (rc) return rc;
+  met::Decoder dec{c, d, pl, static_cast<char *>(workspace), (hipStream_t)stream, B};
+  switch (W) {
+    case 1: return dec.run<1>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    case 2: return dec.run<2>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    case 4: return dec.run<4>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    case 8: return dec.run<8>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    case 16: return dec.run<16>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    case 32: return dec.run<32>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    default: return dec.run<64>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+  }
+}

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP decoder (through the C ABI) against the FP64 oracle.
+
+Tolerance on posteriors: |P_gpu - P_oracle| <= 1e-3 |P_oracle| + 1e-4 over the
+first 20 iterations (FP32 messages against FP64).  Integer results (syndromes,
+convergence flags) are bit-exact; hard bits are compared on frames where both
+sides converged (on other frames several decisions are equally valid).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import paper_1711_01783_amd as met  # noqa: E402
+from oracle import bp, code as oc  # noqa: E402
+from met_inputs import PROFILES, make_frames  # noqa: E402
+
+RTOL, ATOL = 1e-3, 1e-4
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(prof, n, b, snr, seed=11, code_seed=5):
+    code_o = oc.build(PROFILES[prof], n, code_seed)
+    code_g = met.Code.build(PROFILES[prof], n, code_seed)
+    bits, llr = make_frames(n, b, snr, seed)
+    syn = oc.syndrome(code_o, bits)
+    return code_o, code_g, bits, llr, syn
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _gpu_decode(code_g, llr, syn, iters, fixed=True, posterior=True):
+    out = met.decode(code_g, _dev(llr), _dev(syn), iters, fixed_iters=fixed, posterior=posterior)
+    torch.cuda.synchronize()
+    post = out.posterior.cpu().numpy() if posterior else None
+    return out.bits.cpu().numpy(), out.iterations.cpu().numpy(), out.converged.cpu().numpy(), post
+
+
+def test_syndrome_bit_exact():
+    for prof, n, b in (("r0.1", 65536, 5), ("r0.02", 4096, 70)):
+        code_o, code_g, bits, _llr, syn = _case(prof, n, b, 0.2)
+        print("syndrome", prof, n, b, flush=True)
+        got = met.syndrome(code_g, _dev(bits)).cpu().numpy()
+        np.testing.assert_array_equal(got, syn)
+
+
+POSTERIOR_CASES = [
+    # (profile, N, frames, SNR): W = 64 / ragged groups / W = 1 / W = 4 / other rates
+    ("r0.1", 16384, 64, 0.205),
+    ("r0.1", 4096, 100, 0.157),
+    ("r0.05", 8192, 8, 0.105),
+    ("r0.02", 8192, 33, 0.068),
+    ("r0.1", 4096, 1, 0.25),
+    ("r0.02", 4096, 3, 0.0296),
+]
+
+
+@pytest.mark.parametrize("prof,n,b,snr", POSTERIOR_CASES)
+def test_posterior_parity_first_20_iterations(prof, n, b, snr):
+    code_o, code_g, bits, llr, syn = _case(prof, n, b, snr)
+    iters = [1, 2, 3, 5, 10, 20]
+    ref = bp.decode(code_o, llr, syn, max(iters), early_exit=False, trace_iters=iters)
+    for it in iters:
+        print("posterior", prof, n, b, snr, "iteration", it, flush=True)
+        gbits, giters, gconv, gpost = _gpu_decode(code_g, llr, syn, it)
+        r = ref.trace[it]
+        err = np.abs(gpost - r)
+        bad = err > RTOL * np.abs(r) + ATOL
+        assert not bad.any(), "iteration %d: %d violations, worst %g at P=%g" % (
+            it, bad.sum(), err.max(), r.flat[np.argmax(err)])
+        np.testing.assert_array_equal(giters, it)
+        # converged must equal the exact syndrome test of the GPU's own bits
+        np.testing.assert_array_equal(gconv, np.all(oc.syndrome(code_o, gbits) == syn, axis=1).astype(np.uint8))
+        # hard bits agree with the posterior sign away from ties
+        clear = np.abs(gpost) > 1e-3
+        np.testing.assert_array_equal(gbits[clear], (gpost[clear] < 0).astype(np.uint8))
+
+
+@pytest.mark.parametrize("prof,n,b,snr,max_iter", [("r0.1", 65536, 16, 0.25, 60), ("r0.05", 16384, 40, 0.11, 80)])
+def test_early_exit_parity(prof, n, b, snr, max_iter):
+    code_o, code_g, bits, llr, syn = _case(prof, n, b, snr, seed=21)
+    ref = bp.decode(code_o, llr, syn, max_iter)
+    print("early exit", prof, n, b, snr, flush=True)
+    gbits, giters, gconv, gpost = _gpu_decode(code_g, llr, syn, max_iter, fixed=False)
+    both = (gconv == 1) & (ref.converged == 1)
+    assert both.sum() >= b // 2
+    np.testing.assert_array_equal(gbits[both], ref.bits[both])
+    assert np.all(np.abs(giters[both].astype(int) - ref.iterations[both]) <= 1)
+    np.testing.assert_array_equal(gconv, np.all(oc.syndrome(code_o, gbits) == syn, axis=1).astype(np.uint8))
+    np.testing.assert_array_equal(giters[gconv == 0], max_iter)
+    # a frame's early-exit output equals a fixed-iteration run stopped at its count
+    for f in np.nonzero(gconv)[0][:3]:
+        fb, _, fc, fp = _gpu_decode(code_g, llr[f:f + 1], syn[f:f + 1], int(giters[f]))
+        assert fc[0] == 1
+        np.testing.assert_array_equal(fb[0], gbits[f])
+        np.testing.assert_array_equal(fp[0], gpost[f])
+
+
+def test_tree_codes_generic_shapes_match_map():
+    """Hand-built tree codes exercise the run-time-degree check kernel."""
+    from oracle import map as omap
+    from tests.trees import random_tree
+
+    for seed in range(6):
+        rng = np.random.default_rng(seed)
+        n, m, v, c, t = random_tree(14, rng)
+        code_o = oc.from_edges(n, m, v, c, t, n_edge_types=3)
+        code_g = met.Code.from_edges(n, m, v, c, t)
+        x = rng.integers(0, 2, n).astype(np.uint8)
+        s = oc.syndrome(code_o, x)
+        llr = rng.normal(0.3, 1.5, (1, n)).astype(np.float32)
+        _, _, _, gpost = _gpu_decode(code_g, llr, s, 2 * n)
+        exact = omap.posteriors(code_o, llr[0].astype(np.float64), s[0])
+        np.testing.assert_allclose(gpost[0], exact, rtol=RTOL, atol=ATOL)
+
+
+def test_sign_symmetry_bit_exact():
+    """decode(L, Hx) == (1-2x) * decode((1-2x) L, 0), exactly, in FP32."""
+    code_o, code_g, bits, llr, syn = _case("r0.1", 16384, 64, 0.19)
+    flip = (1.0 - 2.0 * bits).astype(np.float32)
+    a = _gpu_decode(code_g, llr, syn, 15)
+    b = _gpu_decode(code_g, flip * llr, np.zeros_like(syn), 15)
+    np.testing.assert_array_equal(a[3], flip * b[3])
+    np.testing.assert_array_equal(a[2], b[2])
+    nz = a[3] != 0
+    np.testing.assert_array_equal(a[0][nz], (b[0] ^ bits)[nz])
+
+
+def test_batch_invariance_and_determinism():
+    """A frame's result does not depend on its batch, interleave or group."""
+    code_o, code_g, bits, llr, syn = _case("r0.02", 8192, 100, 0.07)
+    full = _gpu_decode(code_g, llr, syn, 40, fixed=False)
+    again = _gpu_decode(code_g, llr, syn, 40, fixed=False)
+    for x, y in zip(full, again):
+        np.testing.assert_array_equal(x, y)
+    for lo, hi in ((0, 1), (5, 8), (64, 100), (30, 47)):
+        sub = _gpu_decode(code_g, llr[lo:hi], syn[lo:hi], 40, fixed=False)
+        for x, y in zip(full, sub):
+            np.testing.assert_array_equal(x[lo:hi], y)
+
+
+def test_nan_frame_does_not_affect_neighbours():
+    code_o, code_g, bits, llr, syn = _case("r0.1", 8192, 8, 0.25)
+    ref = _gpu_decode(code_g, llr, syn, 30, fixed=False)
+    bad = llr.copy()
+    bad[3, ::7] = np.nan
+    got = _gpu_decode(code_g, bad, syn, 30, fixed=False)
+    keep = np.arange(8) != 3
+    for x, y in zip(ref, got):
+        np.testing.assert_array_equal(x[keep], y[keep])
+
+
+def test_failure_injection_from_host():
+    """Corrupted syndromes, one-iteration budgets and sub-threshold noise give
+    consistent flags (converged iff H bits = target) and bounded iteration counts."""
+    code_o, code_g, bits, llr, syn = _case("r0.1", 8192, 8, 0.25)
+    flipped = syn.copy()
+    flipped[:, :2] ^= 1
+    out = _gpu_decode(code_g, llr, flipped, 5, fixed=False)
+    assert np.all((out[1] >= 1) & (out[1] <= 5))
+    np.testing.assert_array_equal(out[2], np.all(oc.syndrome(code_o, out[0]) == flipped, axis=1).astype(np.uint8))
+    one = _gpu_decode(code_g, llr, syn, 1, fixed=False)
+    np.testing.assert_array_equal(one[1], 1)
+    np.testing.assert_array_equal(one[2], np.all(oc.syndrome(code_o, one[0]) == syn, axis=1).astype(np.uint8))
+    far = _case("r0.1", 8192, 8, 0.03)
+    out = _gpu_decode(far[1], far[3], far[4], 10, fixed=False)
+    np.testing.assert_array_equal(out[2], 0)
+    np.testing.assert_array_equal(out[1], 10)

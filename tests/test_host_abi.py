@@ -1,0 +1,149 @@
+"""Host-side tests of the C ABI (no GPU): construction parity, validation, exports."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1711_01783_amd as met
+from paper_1711_01783_amd import _lib
+from oracle import code as oc
+from met_inputs import PROFILES, Profile
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "met_bp.h")).read()
+    names = set(re.findall(r"\b(met_[a-z_0-9]+)\s*\(", hdr))
+    assert {"met_code_build", "met_decode", "met_syndrome", "met_last_error"} <= names
+    so = ctypes.CDLL(_lib.library_path)
+    for n in sorted(names):
+        assert hasattr(so, n), n
+
+
+@pytest.mark.parametrize("name", list(PROFILES))
+@pytest.mark.parametrize("n,seed", [(4096, 1), (20000, 7), (65536, 123456789)])
+def test_cpp_builder_matches_oracle_construction(name, n, seed):
+    prof = PROFILES[name]
+    a = oc.build(prof, n, seed)
+    b = met.Code.build(prof, n, seed)
+    vn, cn, et = b.export()
+    assert b.N == a.n and b.M == a.m and b.E == a.e
+    np.testing.assert_array_equal(vn, a.v)
+    np.testing.assert_array_equal(cn, a.c)
+    np.testing.assert_array_equal(et, a.t)
+    st = b.info()
+    sa = a.stats()
+    for k in ("N", "M", "E", "E_type", "n_deg1", "edges_to_pass"):
+        assert st[k] == sa[k], k
+
+
+def test_cpp_builder_repairs_like_oracle():
+    prof = Profile("dense", 0.5, vn_types=((1.0, (3,)),), cn_types=((0.5, (6,)),))
+    for seed in range(5):
+        a = oc.build(prof, 40, seed)
+        vn, cn, et = met.Code.build(prof, 40, seed).export()
+        np.testing.assert_array_equal(vn, a.v)
+        np.testing.assert_array_equal(cn, a.c)
+
+
+def test_full_length_statistics():
+    """Rate-0.1 profile at N = 10^6 (Table 1 style bookkeeping)."""
+    st = met.Code.build(PROFILES["r0.1"], 10**6, 2024).info()
+    assert (st["M"], st["E"], st["n_deg1"], st["edges_to_pass"]) == (900000, 3760000, 880000, 2880000)
+    assert st["n_msg_vn"] == 120000 and st["n_msg_edges"] == 2880000 and st["n_leaf_edges"] == 880000
+    assert st["max_check_degree"] == 12 and st["max_vn_degree"] == 24
+    assert st["n_check_classes"] == 2
+
+
+def test_check_classes_cover_irregular_runs():
+    st = met.Code.build(PROFILES["r0.1"], 65536, 1).info()
+    # 4 checks of degree 11, 1307 of degree 12, 8 checks with (2 + 1), the rest (3 + 1)
+    assert st["n_check_classes"] == 4
+
+
+def test_from_edges_roundtrip_and_sorting():
+    vn = [2, 0, 1, 1, 3]
+    cn = [1, 0, 0, 1, 1]
+    c = met.Code.from_edges(4, 2, vn, cn, [0, 1, 2, 0, 1])
+    v, ch, t = c.export()
+    np.testing.assert_array_equal(ch, [0, 0, 1, 1, 1])
+    # sorted by (check, type, VN)
+    np.testing.assert_array_equal(v, [0, 1, 1, 2, 3])
+    np.testing.assert_array_equal(t, [1, 2, 0, 0, 1])
+    assert c.info()["n_deg1"] == 3
+
+
+@pytest.mark.parametrize(
+    "args,msg",
+    [
+        ((4, 2, [0, 5], [0, 1]), "out of range"),
+        ((4, 1, [0, 0, 1], [0, 0, 0]), "repeated"),
+        ((4, 2, [0, 1, 2], [0, 0, 1]), "degree 1"),
+    ],
+)
+def test_from_edges_validation(args, msg):
+    with pytest.raises(met.MetError) as e:
+        met.Code.from_edges(*args)
+    assert e.value.code == -1
+    assert msg in str(e.value)
+
+
+def test_profile_validation():
+    bad = Profile("bad", 0.5, vn_types=((0.5, (2, 1)), (0.5, (0, 1))), cn_types=((0.5, (2, 1)), (0.1, (0, 2))))
+    with pytest.raises(met.MetError, match="two check types"):
+        met.Code.build(bad, 100, 1)
+    bad2 = Profile("bad2", 0.5, vn_types=((1.0, (3,)),), cn_types=((0.9, (6,)),))
+    with pytest.raises(met.MetError, match="cn_frac"):
+        met.Code.build(bad2, 1000, 1)
+    with pytest.raises(met.MetError):
+        met.Code.build(PROFILES["r0.1"], 1, 1)
+
+
+def test_decode_argument_validation_without_gpu():
+    """Validation happens before any HIP call, so it works on a GPU-less host."""
+    c = met.Code.build(PROFILES["r0.1"], 4096, 1)
+    L = _lib.lib
+    P = ctypes.c_void_p
+    dummy = P(256)
+    n = ctypes.c_size_t()
+    assert L.met_decode_workspace_bytes(c.handle, 0, 0, 0, ctypes.byref(n)) == -1
+    assert L.met_decode_workspace_bytes(c.handle, 64, 7, 0, ctypes.byref(n)) == -1
+    assert L.met_decode_workspace_bytes(None, 64, 0, 0, ctypes.byref(n)) == -1
+    assert L.met_decode_workspace_bytes(c.handle, 64, 0, 0, ctypes.byref(n)) == 0 and n.value > 0
+    big = n.value
+    args = dict(llr=dummy, syn=dummy, B=64, it=10, flags=0, bits=dummy, iters=dummy, conv=dummy, post=None,
+                ws=dummy, wsb=big)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return L.met_decode(c.handle, a["llr"], a["syn"], a["B"], a["it"], a["flags"], a["bits"], a["iters"],
+                            a["conv"], a["post"], a["ws"], a["wsb"], None)
+
+    assert call(B=0) == -1
+    assert call(it=0) == -1
+    assert call(llr=None) == -1
+    assert call(llr=P(258)) == -1          # misaligned float buffer
+    assert call(ws=P(264)) == -1           # workspace not 256-byte aligned
+    assert call(wsb=big - 1) == -1         # too small
+    assert call(flags=4) == -1
+    assert "workspace" in L.met_last_error().decode() or "flags" in L.met_last_error().decode()
+    assert L.met_syndrome(c.handle, None, 1, dummy, None) == -1
+    assert L.met_syndrome(c.handle, dummy, 0, dummy, None) == -1
+
+
+def test_workspace_grows_with_batch_and_posterior():
+    c = met.Code.build(PROFILES["r0.05"], 8192, 3)
+    a = met.workspace_bytes(c, 1)
+    b = met.workspace_bytes(c, 64)
+    d = met.workspace_bytes(c, 64, posterior=True)
+    assert a < b < d
+
+
+def test_free_is_idempotent():
+    c = met.Code.build(PROFILES["r0.02"], 2048, 3)
+    c.close()
+    c.close()
+    _lib.lib.met_code_free(None)
