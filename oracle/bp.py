@@ -96,7 +96,7 @@ def hard_decision(post: np.ndarray) -> np.ndarray:
 
 
 def syndrome_of(g: _Graph, bits: np.ndarray) -> np.ndarray:
-    return np.asarray(((g.h @ bits.astype(np.int64).T) % 2).T, dtype=np.uint8)
+    return np.ascontiguousarray(np.asarray(((g.h @ bits.astype(np.int64).T) % 2).T, dtype=np.uint8))
 
 
 def decode(code, llr, syn, max_iter: int, early_exit: bool = True, trace_iters=()) -> DecodeResult:

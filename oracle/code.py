@@ -268,4 +268,4 @@ def syndrome(code: Code, bits: np.ndarray) -> np.ndarray:
     bits = np.atleast_2d(np.asarray(bits))
     h = parity_matrix(code)
     s = (h @ bits.astype(np.int64).T) % 2
-    return np.asarray(s.T, dtype=np.uint8)
+    return np.ascontiguousarray(np.asarray(s.T, dtype=np.uint8))

@@ -64,19 +64,48 @@ POSTERIOR_CASES = [
 ]
 
 
+def _perturbed(llr, seed=0):
+    """The same LLRs moved by about one FP32 rounding (relative 1e-7), in FP64."""
+    rng = np.random.default_rng(seed)
+    return llr.astype(np.float64) * (1.0 + 1e-7 * rng.standard_normal(llr.shape))
+
+
 @pytest.mark.parametrize("prof,n,b,snr", POSTERIOR_CASES)
 def test_posterior_parity_first_20_iterations(prof, n, b, snr):
+    """Element-wise parity wherever the computation is well conditioned.
+
+    The FP64 oracle is rerun on the inputs moved by about one FP32 rounding
+    (relative 1e-7, two independent draws); `spread` is the element-wise largest
+    change of its posteriors.  An iteration is well conditioned when the spread
+    stays below a quarter of the tolerance everywhere; there the GPU must meet
+    the tolerance element by element, and iterations 1-10 must all be well
+    conditioned.  Near the BP threshold flooding BP amplifies such a
+    perturbation past 1e-3 within 20 iterations even in FP64; in those
+    iterations the GPU may only miss the tolerance where the oracle's own
+    spread is large: at most 4x as many elements, and by at most 4x the spread.
+    """
     code_o, code_g, bits, llr, syn = _case(prof, n, b, snr)
-    iters = [1, 2, 3, 5, 10, 20]
+    iters = [1, 2, 3, 5, 10, 15, 20]
     ref = bp.decode(code_o, llr, syn, max(iters), early_exit=False, trace_iters=iters)
+    perts = [bp.decode(code_o, _perturbed(llr, sd), syn, max(iters), early_exit=False, trace_iters=iters)
+             for sd in (0, 1)]
     for it in iters:
         print("posterior", prof, n, b, snr, "iteration", it, flush=True)
         gbits, giters, gconv, gpost = _gpu_decode(code_g, llr, syn, it)
         r = ref.trace[it]
+        tol = RTOL * np.abs(r) + ATOL
         err = np.abs(gpost - r)
-        bad = err > RTOL * np.abs(r) + ATOL
-        assert not bad.any(), "iteration %d: %d violations, worst %g at P=%g" % (
-            it, bad.sum(), err.max(), r.flat[np.argmax(err)])
+        spread = np.maximum.reduce([np.abs(q.trace[it] - r) for q in perts])
+        bad, sensitive = err > tol, spread > tol / 4
+        if not sensitive.any():
+            assert not bad.any(), "iteration %d: %d violations, worst %g at P=%g" % (
+                it, bad.sum(), err.max(), r.flat[np.argmax(err)])
+        else:
+            assert it > 10, "oracle ill-conditioned already at iteration %d" % it
+            print("  ill-conditioned: %d elements with spread > tol/4 (max spread %.3g); GPU %d violations"
+                  " (worst %.3g)" % (sensitive.sum(), spread.max(), bad.sum(), err.max()), flush=True)
+            assert bad.sum() <= 4 * sensitive.sum() + 10
+            assert err.max() <= 4 * spread.max()
         np.testing.assert_array_equal(giters, it)
         # converged must equal the exact syndrome test of the GPU's own bits
         np.testing.assert_array_equal(gconv, np.all(oc.syndrome(code_o, gbits) == syn, axis=1).astype(np.uint8))
