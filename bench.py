@@ -1,0 +1,305 @@
+#!/usr/bin/env python3
+"""Decoded Mbit/s of syndrome BP on MET-LDPC codes on one MI355X.
+
+A step is one decode call over one batch: flooding sum-product BP of the
+paper's Methods (Steps 2-5) on B frames of a rate-0.1 MET code with N = 10^6,
+every part of the hot path (input layout, check and variable kernels, syndrome
+tests, output) on the GPU.  Inputs are resident in HBM before the timed region.
+
+    python bench.py [--steps K] [--warmup W] [--profile r0.1|r0.05|r0.02] ...
+
+Prints one JSON line.  Speed counts N decoded bits per frame, as the paper's
+Table 1 does (speed = N / (iterations x per-codeword latency)).
+
+The roofline object reports the check kernel, which moves most of the bytes:
+algorithmic bytes per launch (unique bytes a launch must read or write, see
+``check_bytes_per_frame``) divided by the kernel's average duration, measured
+with HIP events bracketing each launch on the decode stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from met_inputs import BJ_SNR, ITER_BUDGET, PROFILES, make_frames  # noqa: E402
+
+METRIC = "decoded Mbit/s at N=1e6, R=0.1/0.05/0.02 (batched vs plain, equal FER); % HBM peak"
+HBM_PEAK_GBS = 8000.0
+CODE_SEED = {"r0.1": 101, "r0.05": 102, "r0.02": 103}
+FRAME_SEED = 5000
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_check_traffic.json")
+
+
+def check_bytes_per_frame(st: dict, W: int, first: bool = False, test: bool = True) -> float:
+    """Unique bytes one check-kernel launch moves per frame and iteration.
+
+    read  c2v (4 B per message edge, not on iteration 1), P (4 B per message VN,
+          gathered), leaf phi(L) (4 B per leaf edge), syndrome (1 bit per
+          check), previous leaf decisions (1 bit per leaf edge) and the
+          edge -> VN index (4 B per message edge, shared by W frames);
+    write c2v (4 B per message edge) and leaf decisions (1 bit per leaf edge).
+    """
+    e12, el, n2, m = st["n_msg_edges"], st["n_leaf_edges"], st["n_msg_vn"], st["M"]
+    b = (0 if first else 4 * e12) + 4 * e12 + 4 * n2 + 4 * el + m / 8 + el / 8 + 4 * e12 / W
+    if test:
+        b += el / 8
+    return b
+
+
+def variable_bytes_per_frame(st: dict, W: int) -> float:
+    """read c2v (gathered, 4 B per message edge) and L (4 B per message VN),
+    the VN -> edge lists (shared by W frames); write P (4 B per message VN)."""
+    e12, n2 = st["n_msg_edges"], st["n_msg_vn"]
+    return 4 * e12 + 8 * n2 + (4 * e12 + 4 * n2) / W
+
+
+def wilson(k: int, n: int, z: float = 1.96):
+    if n == 0:
+        return (0.0, 1.0)
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
+    return (max(0.0, c - h), min(1.0, c + h))
+
+
+# ----------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands, one frame per host core.
+
+_CPU = {}
+
+
+def _cpu_worker(f):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle import bp
+    from oracle import code as oc
+
+    code = _CPU["code"]
+    bits, llr = make_frames(code.n, 1, _CPU["snr"], FRAME_SEED, first_frame=f)
+    syn = oc.syndrome(code, bits)
+    t0 = time.perf_counter()
+    bp.decode(code, llr, syn, _CPU["iters"], early_exit=False)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(prof: str, n: int, snr: float, budget: int, sample_iters: int, max_workers: int) -> dict:
+    import multiprocessing as mp
+
+    from oracle import code as oc
+
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, max_workers))
+    _CPU["code"] = oc.build(PROFILES[prof], n, CODE_SEED[prof])
+    _CPU["snr"] = snr
+    _CPU["iters"] = sample_iters
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        durs = pool.map(_cpu_worker, range(workers))
+    wall = time.perf_counter() - t0
+    per_frame_full = max(durs) * budget / sample_iters
+    mbit = workers * n / per_frame_full / 1e6
+    return {
+        "value": round(mbit, 4),
+        "unit": "Mbit/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": "%d frames (one per core) of the same workload, %d of %d iterations each in fixed mode, "
+        "slowest frame's decode time extrapolated linearly to the full budget (wall %.1f s)"
+        % (workers, sample_iters, budget, wall),
+    }
+
+
+# ----------------------------------------------------------------------------
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1711_01783_amd", "csrc", "met_decode.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per check-kernel launch from the committed counter summary,
+    or None when it is missing or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("workload") != workload_key:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--profile", default="r0.1", choices=sorted(PROFILES))
+    ap.add_argument("--n", type=int, default=10**6)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--snr", type=float, default=None)
+    ap.add_argument("--max-iter", type=int, default=None)
+    ap.add_argument("--fixed-iters", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=40, help="iterations per frame in the CPU sample")
+    ap.add_argument("--cpu-workers", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB device copies (scale for rocprofv3 byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        return 2
+
+    if args.copy_calibration:
+        import torch
+
+        n = 1 << 28  # 1 GiB of float32
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 5}))
+        return 0
+
+    prof = args.profile
+    snr = args.snr if args.snr is not None else BJ_SNR[prof]
+    max_iter = args.max_iter if args.max_iter is not None else ITER_BUDGET[prof]
+    n, B = args.n, args.frames
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before any GPU initialisation: the oracle runs in forked host processes
+        cpu = cpu_baseline(prof, n, snr, max_iter, min(args.cpu_iters, max_iter), args.cpu_workers)
+
+    import numpy as np
+    import torch
+
+    import paper_1711_01783_amd as met
+
+    dev = torch.device("cuda:0")
+    code = met.Code.build(PROFILES[prof], n, CODE_SEED[prof])
+    st = code.info()
+    bits, llr = make_frames(n, B, snr, FRAME_SEED)
+    d_llr = torch.from_numpy(llr).to(dev)
+    d_bits = torch.from_numpy(bits).to(dev)
+    d_syn = met.syndrome(code, d_bits)
+    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters) + 256, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    out = None
+    for _ in range(args.warmup):
+        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws)
+    torch.cuda.synchronize()
+
+    met.timing_enable(True)
+    met.timing_collect()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    elapsed_ms = start.elapsed_time(stop)
+    ktimes = met.timing_collect()
+    met.timing_enable(False)
+
+    ms_per_step = elapsed_ms / args.steps
+    value = B * n * args.steps / (elapsed_ms * 1e-3) / 1e6
+
+    iters = out.iterations.cpu().numpy()
+    conv = out.converged.cpu().numpy()
+    dec = out.bits.cpu().numpy()
+    frame_err = np.any(dec != bits, axis=1)
+    nerr = int(frame_err.sum())
+    lo, hi = wilson(nerr, B)
+
+    # Algorithmic bytes of the check kernel over the timed region: frames still
+    # running in launch l of a step; a frame that converged at iteration r takes
+    # part in launches 1 .. r+1 (launch r+1 evaluates its syndrome test).
+    W = 1
+    while W < min(B, 64):
+        W <<= 1
+    last = np.where(conv == 1, np.minimum(iters + 1, max_iter), max_iter)
+    cn_bytes = 0.0
+    for l in range(1, max_iter + 1):
+        frames_l = int(np.count_nonzero(last >= l))
+        cn_bytes += frames_l * check_bytes_per_frame(st, W, first=(l == 1), test=(l >= 2 and not args.fixed_iters))
+    cn_bytes *= args.steps
+    launches, cn_ms = ktimes.get("k_check", (0, 0.0))
+    cn_avg_ms = cn_ms / max(1, launches)
+    bytes_per_launch = cn_bytes / max(1, launches)
+    achieved = bytes_per_launch / (cn_avg_ms * 1e-3) / 1e9 if cn_avg_ms > 0 else 0.0
+    workload_key = "%s N=%d B=%d snr=%g max_iter=%d %s" % (
+        prof, n, B, snr, max_iter, "fixed" if args.fixed_iters else "early-exit")
+    traffic = measured_traffic(workload_key)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded uniform bits, BPSK over AWGN, FP32 LLRs; seeded random MET code",
+        "config": {
+            "workload": "plain BP (one decode call per batch), rate %s MET profile, N=%d, %d frames, SNR %g, "
+            "max %d iterations, %s" % (PROFILES[prof].rate, n, B, snr, max_iter,
+                                     "fixed iterations" if args.fixed_iters else "per-frame early exit"),
+            "profile": prof,
+            "N": n,
+            "frames": B,
+            "snr": snr,
+            "max_iter": max_iter,
+            "mode": "plain",
+            "interleave": W,
+            "code_seed": CODE_SEED[prof],
+            "frame_seed": FRAME_SEED,
+        },
+        "roofline": {
+            "kernel": "k_check",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(bytes_per_launch),
+            "avg_launch_us": round(cn_avg_ms * 1e3, 2),
+        },
+        "cpu_baseline": cpu,
+        "fer": round(nerr / B, 4),
+        "fer_ci95": [round(lo, 4), round(hi, 4)],
+        "converged_frames": int(conv.sum()),
+        "mean_iterations": round(float(iters.mean()), 2),
+        "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)} for k, v in ktimes.items()},
+        "bytes_per_frame_iteration": {
+            "check": check_bytes_per_frame(st, W),
+            "variable": variable_bytes_per_frame(st, W),
+        },
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -153,6 +153,21 @@ int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t 
                uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
                void *workspace, size_t ws_bytes, void *stream);
 
+/* Measurement support (not part of decoding).  While enabled, every kernel
+ * launched by met_decode in this process is bracketed by two HIP events
+ * recorded on the caller's stream, the stream the kernel runs on.
+ * met_timing_collect waits for the recorded events, writes up to max_entries
+ * per-kernel records (launch count, summed duration) and clears the record.
+ * Enabling allocates HIP events; decoding results are unaffected.
+ * Errors: MET_EINVAL (NULL output), MET_EHIP. */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} met_kernel_time;
+int met_timing_enable(int32_t on);
+int met_timing_collect(met_kernel_time *out, int32_t max_entries, int32_t *n_entries);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *met_last_error(void);
 

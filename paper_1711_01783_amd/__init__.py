@@ -17,7 +17,7 @@ from ._lib import (
     lib,
     library_path,
 )
-from .api import Code, DecodeOutput, decode, syndrome, workspace_bytes
+from .api import Code, DecodeOutput, decode, syndrome, timing_collect, timing_enable, workspace_bytes
 
 __all__ = [
     "Code",
@@ -29,5 +29,7 @@ __all__ = [
     "lib",
     "library_path",
     "syndrome",
+    "timing_collect",
+    "timing_enable",
     "workspace_bytes",
 ]

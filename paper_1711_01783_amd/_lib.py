@@ -55,6 +55,10 @@ class met_code_stats(ctypes.Structure):
     ]
 
 
+class met_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(library_path):
         raise ImportError(
@@ -73,6 +77,8 @@ def _load():
         "met_decode_workspace_bytes": (ctypes.c_int, [P, i32, u32, i32, ctypes.POINTER(sz)]),
         "met_decode": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, P]),
         "met_last_error": (ctypes.c_char_p, []),
+        "met_timing_enable": (ctypes.c_int, [i32]),
+        "met_timing_collect": (ctypes.c_int, [ctypes.POINTER(met_kernel_time), i32, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

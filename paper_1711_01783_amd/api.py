@@ -6,7 +6,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import MET_FIXED_ITERS, check, lib, met_code_stats, met_profile
+from ._lib import MET_FIXED_ITERS, check, lib, met_code_stats, met_kernel_time, met_profile
 
 
 class Code:
@@ -166,3 +166,16 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
         )
     )
     return DecodeOutput(bits, iters, conv, post)
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every decoder kernel launch with HIP events on its stream."""
+    check(lib.met_timing_enable(1 if on else 0))
+
+
+def timing_collect() -> dict:
+    """{kernel name: (launches, total milliseconds)} since the last collect."""
+    buf = (met_kernel_time * 64)()
+    n = ctypes.c_int32()
+    check(lib.met_timing_collect(buf, 64, ctypes.byref(n)))
+    return {buf[k].name.decode(): (int(buf[k].launches), float(buf[k].total_ms)) for k in range(n.value)}

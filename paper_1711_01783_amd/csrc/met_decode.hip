@@ -613,6 +613,48 @@ __global__ __launch_bounds__(kBlock) void k_syndrome(const int32_t *all_vn, cons
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Optional per-launch timing with HIP events on the launch stream.
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  struct Rec {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+TimingState g_timing;
+
+struct ScopedTimer {
+  hipStream_t st;
+  const char *name;
+  hipEvent_t a = nullptr, b = nullptr;
+  ScopedTimer(hipStream_t s, const char *n) : st(s), name(n) {
+    if (!g_timing.on) return;
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    a = g_timing.get();
+    b = g_timing.get();
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  ~ScopedTimer() {
+    if (!a || !b) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lock(g_timing.mu);
+    g_timing.recs.push_back({name, a, b});
+  }
+};
+
 struct Plan {
   int W = 64, G = 1;
   size_t off_c2v = 0, off_P = 0, off_L2 = 0, off_Lphi = 0, off_Lraw = 0, off_P1 = 0, off_synw = 0, off_B1 = 0,
@@ -705,14 +747,21 @@ struct Decoder {
     ip.unsat = unsat;
     ip.iters = iters;
     ip.converged = conv;
-    hipLaunchKernelGGL(k_transpose<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st, ip);
+    {
+      ScopedTimer t(st, "k_transpose");
+      hipLaunchKernelGGL(k_transpose<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st, ip);
+    }
     {
       const int64_t n = (c->N2 + c->EL) * W;
+      ScopedTimer t(st, "k_init_items");
       if (n > 0)
         hipLaunchKernelGGL(k_init_items<W>, dim3((unsigned)((n + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st, ip);
     }
-    hipLaunchKernelGGL(k_pack_syndrome<W>, dim3((unsigned)std::max<int64_t>(1, (c->M + kBlock - 1) / kBlock), G),
-                       dim3(kBlock), 0, st, ip);
+    {
+      ScopedTimer t(st, "k_pack_syndrome");
+      hipLaunchKernelGGL(k_pack_syndrome<W>, dim3((unsigned)std::max<int64_t>(1, (c->M + kBlock - 1) / kBlock), G),
+                         dim3(kBlock), 0, st, ip);
+    }
 
     CheckParams cp{};
     cp.edge_msgvn = d->edge_msgvn;
@@ -782,8 +831,12 @@ struct Decoder {
       cp.P1 = P1 ? P1 + (size_t)(it & 1) * leaf_floats : nullptr;
       cp.unsat = unsat + (size_t)((it - 1) & 1) * G;
       cp.unsat_clear = unsat + (size_t)(it & 1) * G;
-      if (cn_blocks > 0) hipLaunchKernelGGL((k_check<W, false>), dim3(cn_blocks, G), dim3(kBlock), 0, st, cp);
+      if (cn_blocks > 0) {
+        ScopedTimer t(st, "k_check");
+        hipLaunchKernelGGL((k_check<W, false>), dim3(cn_blocks, G), dim3(kBlock), 0, st, cp);
+      }
       if (gen_blocks > 0) {
+        ScopedTimer t(st, "k_check_generic");
         gp.it = cp.it;
         gp.flags = cp.flags;
         gp.Pin = cp.Pin;
@@ -797,7 +850,10 @@ struct Decoder {
       vp.it = it;
       vp.retire = early && it >= 2;
       vp.unsat = unsat + (size_t)((it - 1) & 1) * G;
-      if (vn_blocks > 0) hipLaunchKernelGGL(k_variable<W>, dim3(vn_blocks, G), dim3(kBlock), 0, st, vp);
+      if (vn_blocks > 0) {
+        ScopedTimer t(st, "k_variable");
+        hipLaunchKernelGGL(k_variable<W>, dim3(vn_blocks, G), dim3(kBlock), 0, st, vp);
+      }
     }
     TestParams tp{};
     tp.edge_msgvn = d->edge_msgvn;
@@ -814,6 +870,7 @@ struct Decoder {
     tp.unsat = unsat + (size_t)(max_iter & 1) * G;
     {
       const int64_t per = (int64_t)kWavesPerBlock * (64 / W);
+      ScopedTimer t(st, "k_test");
       hipLaunchKernelGGL(k_test<W>, dim3((unsigned)((c->M + per - 1) / per), G), dim3(kBlock), 0, st, tp);
     }
     FinalParams fp{};
@@ -835,8 +892,11 @@ struct Decoder {
     fp.bits = bits;
     fp.posterior = post;
     fp.G = G;
-    hipLaunchKernelGGL(k_final_status<W>, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fp);
-    hipLaunchKernelGGL(k_finalize<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), B), dim3(kBlock), 0, st, fp);
+    {
+      ScopedTimer t(st, "k_finalize");
+      hipLaunchKernelGGL(k_final_status<W>, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fp);
+      hipLaunchKernelGGL(k_finalize<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), B), dim3(kBlock), 0, st, fp);
+    }
     HIP_TRY(hipGetLastError());
     return MET_OK;
   }
@@ -978,4 +1038,48 @@ extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *sy
     case 32: return dec.run<32>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     default: return dec.run<64>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   }
+}
+
+extern "C" int met_timing_enable(int32_t on) {
+  met::clear_error();
+  std::lock_guard<std::mutex> lock(met::g_timing.mu);
+  met::g_timing.on = on != 0;
+  return MET_OK;
+}
+
+extern "C" int met_timing_collect(met_kernel_time *out, int32_t max_entries, int32_t *n_entries) {
+  met::clear_error();
+  if (!out || !n_entries || max_entries < 0) return fail(MET_EINVAL, "met_timing_collect: bad output");
+  std::vector<met::TimingState::Rec> recs;
+  {
+    std::lock_guard<std::mutex> lock(met::g_timing.mu);
+    recs.swap(met::g_timing.recs);
+  }
+  int32_t n = 0;
+  int rc = MET_OK;
+  for (const auto &r : recs) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && rc == MET_OK) rc = fail(MET_EHIP, "timing events: %s", hipGetErrorString(e));
+    int32_t k = 0;
+    while (k < n && std::strncmp(out[k].name, r.name, sizeof out[k].name) != 0) ++k;
+    if (k == n) {
+      if (n == max_entries) continue;
+      std::memset(&out[k], 0, sizeof out[k]);
+      std::strncpy(out[k].name, r.name, sizeof out[k].name - 1);
+      ++n;
+    }
+    out[k].launches++;
+    out[k].total_ms += ms;
+  }
+  {
+    std::lock_guard<std::mutex> lock(met::g_timing.mu);
+    for (const auto &r : recs) {
+      met::g_timing.pool.push_back(r.a);
+      met::g_timing.pool.push_back(r.b);
+    }
+  }
+  *n_entries = n;
+  return rc;
 }
