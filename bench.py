@@ -39,20 +39,28 @@ FRAME_SEED = 5000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_check_traffic.json")
 
 
-def check_bytes_per_frame(st: dict, W: int, first: bool = False, test: bool = True) -> float:
-    """Unique bytes one check-kernel launch moves per frame and iteration.
+def class_bytes_per_frame(cls: dict, W: int, first: bool = False, test: bool = True) -> float:
+    """Unique bytes one check-kernel launch over a class of checks moves per
+    frame and iteration (n checks of nm message and nl leaf edges each):
 
-    read  c2v (4 B per message edge, not on iteration 1), P (4 B per message VN,
-          gathered), leaf phi(L) (4 B per leaf edge), syndrome (1 bit per
-          check), previous leaf decisions (1 bit per leaf edge) and the
-          edge -> VN index (4 B per message edge, shared by W frames);
+    read  c2v (4 B per message edge; not on iteration 1), the posteriors P of
+          the distinct message VNs the class reaches (4 B each, gathered), leaf
+          phi(L) (4 B per leaf edge), the syndrome (1 bit per check), previous
+          leaf decisions (1 bit per leaf edge, early-exit test only) and the
+          edge -> VN index (4 B per message edge, shared by the W frames);
     write c2v (4 B per message edge) and leaf decisions (1 bit per leaf edge).
     """
-    e12, el, n2, m = st["n_msg_edges"], st["n_leaf_edges"], st["n_msg_vn"], st["M"]
-    b = (0 if first else 4 * e12) + 4 * e12 + 4 * n2 + 4 * el + m / 8 + el / 8 + 4 * e12 / W
+    n, nm, nl = cls["n_checks"], cls["n_msg"], cls["n_leaf"]
+    b = (0 if first else 4 * nm * n) + 4 * nm * n + 4 * cls["n_msg_vn_touched"] + 4 * nl * n
+    b += n / 8 + nl * n / 8 + 4 * nm * n / W
     if test:
-        b += el / 8
+        b += nl * n / 8
     return b
+
+
+def check_bytes_per_frame(classes: list, W: int, first: bool = False, test: bool = True) -> float:
+    """Sum over the check classes (all check kernels of one iteration)."""
+    return sum(class_bytes_per_frame(c, W, first, test) for c in classes if c["n_msg"] >= 0)
 
 
 def variable_bytes_per_frame(st: dict, W: int) -> float:
@@ -152,6 +160,8 @@ def main() -> int:
     ap.add_argument("--snr", type=float, default=None)
     ap.add_argument("--max-iter", type=int, default=None)
     ap.add_argument("--fixed-iters", action="store_true")
+    ap.add_argument("--check-steps", type=int, default=0, help="check-kernel steps per wave (0 = default)")
+    ap.add_argument("--vn-chunk", type=int, default=0, help="variable-kernel gathers in flight (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
@@ -202,7 +212,8 @@ def main() -> int:
 
     out = None
     for _ in range(args.warmup):
-        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws)
+        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
+                         check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
     torch.cuda.synchronize()
 
     met.timing_enable(True)
@@ -211,7 +222,8 @@ def main() -> int:
     torch.cuda.synchronize()
     start.record()
     for _ in range(args.steps):
-        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws)
+        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
+                         check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
     stop.record()
     torch.cuda.synchronize()
     elapsed_ms = start.elapsed_time(stop)
@@ -228,25 +240,29 @@ def main() -> int:
     nerr = int(frame_err.sum())
     lo, hi = wilson(nerr, B)
 
-    # Algorithmic bytes of the check kernel over the timed region: frames still
-    # running in launch l of a step; a frame that converged at iteration r takes
-    # part in launches 1 .. r+1 (launch r+1 evaluates its syndrome test).
-    W = 1
-    while W < min(B, 64):
-        W <<= 1
+    # Algorithmic bytes of the dominant check kernel over the timed region:
+    # frames still running in launch l of a step; a frame that converged at
+    # iteration r takes part in launches 1 .. r+1 (launch r+1 runs its test).
+    W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 64
+    classes = code.classes()
+    dom = max((c for c in classes if c["n_msg"] >= 0), key=lambda c: c["n_checks"] * (c["n_msg"] + c["n_leaf"]))
+    kname = "k_check<%d,%d>" % (dom["n_msg"], dom["n_leaf"])
     last = np.where(conv == 1, np.minimum(iters + 1, max_iter), max_iter)
     cn_bytes = 0.0
     for l in range(1, max_iter + 1):
         frames_l = int(np.count_nonzero(last >= l))
-        cn_bytes += frames_l * check_bytes_per_frame(st, W, first=(l == 1), test=(l >= 2 and not args.fixed_iters))
+        cn_bytes += frames_l * class_bytes_per_frame(dom, W, first=(l == 1), test=(l >= 2 and not args.fixed_iters))
     cn_bytes *= args.steps
-    launches, cn_ms = ktimes.get("k_check", (0, 0.0))
+    launches, cn_ms = ktimes.get(kname, (0, 0.0))
     cn_avg_ms = cn_ms / max(1, launches)
     bytes_per_launch = cn_bytes / max(1, launches)
     achieved = bytes_per_launch / (cn_avg_ms * 1e-3) / 1e9 if cn_avg_ms > 0 else 0.0
     workload_key = "%s N=%d B=%d snr=%g max_iter=%d %s" % (
         prof, n, B, snr, max_iter, "fixed" if args.fixed_iters else "early-exit")
     traffic = measured_traffic(workload_key)
+    iter_ms = sum(v[1] for k, v in ktimes.items() if k.startswith("k_check") or k == "k_variable")
+    iter_bytes = args.steps * max_iter * B * (check_bytes_per_frame(classes, W) + variable_bytes_per_frame(
+        code.info(), W))
 
     rec = {
         "metric": METRIC,
@@ -276,7 +292,7 @@ def main() -> int:
             "frame_seed": FRAME_SEED,
         },
         "roofline": {
-            "kernel": "k_check",
+            "kernel": kname,
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -293,9 +309,11 @@ def main() -> int:
         "mean_iterations": round(float(iters.mean()), 2),
         "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)} for k, v in ktimes.items()},
         "bytes_per_frame_iteration": {
-            "check": check_bytes_per_frame(st, W),
+            "check": check_bytes_per_frame(classes, W),
             "variable": variable_bytes_per_frame(st, W),
         },
+        "iteration_kernels_gbs": round(iter_bytes / (iter_ms * 1e-3) / 1e9, 1) if iter_ms > 0 else None,
+        "tuning": {"check_steps_per_wave": args.check_steps, "variable_chunk": args.vn_chunk},
     }
     print(json.dumps(rec), flush=True)
     return 0

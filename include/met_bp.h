@@ -110,6 +110,20 @@ int met_code_from_edges(int64_t N, int64_t M, int64_t E, const int32_t *vn, cons
 /* Fills *out (host).  Errors: MET_EINVAL on NULL. */
 int met_code_info(const met_code *c, met_code_stats *out);
 
+/* A run of consecutive checks that one check kernel handles: n_msg edges to
+ * variable nodes of degree >= 2 and n_leaf edges to degree-1 variable nodes per
+ * check (-1 for runs of mixed shapes), and the number of distinct variable
+ * nodes of degree >= 2 those checks reach. */
+typedef struct {
+  int32_t n_msg, n_leaf;
+  int64_t first_check, n_checks;
+  int64_t n_msg_vn_touched;
+} met_check_class;
+
+/* Copies up to max_entries check classes of the code (host array) and their
+ * count into *n.  Errors: MET_EINVAL on NULL. */
+int met_code_classes(const met_code *c, met_check_class *out, int32_t max_entries, int32_t *n);
+
 /* Copies the edge list in check order into host arrays of length E.  Any of
  * vn / cn / etype may be NULL.  Errors: MET_EINVAL on a NULL code. */
 int met_code_export(const met_code *c, int32_t *vn, int32_t *cn, int8_t *etype);
@@ -167,6 +181,22 @@ typedef struct {
 } met_kernel_time;
 int met_timing_enable(int32_t on);
 int met_timing_collect(met_kernel_time *out, int32_t max_entries, int32_t *n_entries);
+
+/* Launch-shape choices for met_decode_ex; 0 in a field selects the default. */
+typedef struct {
+  int32_t check_steps_per_wave; /* 1, 2 or 4: steps of 64/W checks each wave of
+                                   the check kernel loads before computing
+                                   (groups of 64 frames only); default 4 */
+  int32_t variable_chunk;       /* 8, 16 or 32: message gathers the variable
+                                   kernel keeps in flight; default 16 */
+  int32_t reserved[6];          /* must be 0 */
+} met_tuning;
+
+/* met_decode with explicit launch shapes (tuning may be NULL).  Results do not
+ * depend on the tuning.  Errors: as met_decode, MET_EINVAL for bad tuning. */
+int met_decode_ex(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
+                  uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
+                  void *workspace, size_t ws_bytes, const met_tuning *tuning, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *met_last_error(void);

@@ -59,6 +59,16 @@ class met_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class met_tuning(ctypes.Structure):
+    _fields_ = [("check_steps_per_wave", ctypes.c_int32), ("variable_chunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class met_check_class(ctypes.Structure):
+    _fields_ = [("n_msg", ctypes.c_int32), ("n_leaf", ctypes.c_int32), ("first_check", ctypes.c_int64),
+                ("n_checks", ctypes.c_int64), ("n_msg_vn_touched", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(library_path):
         raise ImportError(
@@ -72,11 +82,13 @@ def _load():
         "met_code_from_edges": (ctypes.c_int, [i64, i64, i64, P, P, P, ctypes.POINTER(P)]),
         "met_code_info": (ctypes.c_int, [P, ctypes.POINTER(met_code_stats)]),
         "met_code_export": (ctypes.c_int, [P, P, P, P]),
+        "met_code_classes": (ctypes.c_int, [P, ctypes.POINTER(met_check_class), i32, ctypes.POINTER(i32)]),
         "met_code_free": (None, [P]),
         "met_syndrome": (ctypes.c_int, [P, P, i32, P, P]),
         "met_decode_workspace_bytes": (ctypes.c_int, [P, i32, u32, i32, ctypes.POINTER(sz)]),
         "met_decode": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, P]),
         "met_last_error": (ctypes.c_char_p, []),
+        "met_decode_ex": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, ctypes.POINTER(met_tuning), P]),
         "met_timing_enable": (ctypes.c_int, [i32]),
         "met_timing_collect": (ctypes.c_int, [ctypes.POINTER(met_kernel_time), i32, ctypes.POINTER(i32)]),
     }

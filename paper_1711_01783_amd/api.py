@@ -6,7 +6,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import MET_FIXED_ITERS, check, lib, met_code_stats, met_kernel_time, met_profile
+from ._lib import MET_FIXED_ITERS, check, lib, met_check_class, met_code_stats, met_kernel_time, met_profile, met_tuning
 
 
 class Code:
@@ -66,6 +66,16 @@ class Code:
             "max_check_degree": int(st.max_check_degree),
             "max_vn_degree": int(st.max_vn_degree),
         }
+
+    def classes(self) -> list:
+        """Check classes: dicts with n_msg, n_leaf (-1 for mixed runs),
+        first_check, n_checks, n_msg_vn_touched."""
+        buf = (met_check_class * 64)()
+        n = ctypes.c_int32()
+        check(lib.met_code_classes(self._h, buf, 64, ctypes.byref(n)))
+        return [
+            {f: int(getattr(buf[k], f)) for f, _ in met_check_class._fields_} for k in range(min(64, n.value))
+        ]
 
     def export(self):
         """(vn int32 [E], cn int32 [E], etype int8 [E]) in check order."""
@@ -138,8 +148,11 @@ class DecodeOutput:
 
 
 def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, posterior: bool = False,
-           workspace=None, stream=None) -> DecodeOutput:
-    """Decode llr float32 [B, N] against syn uint8 [B, M] (device tensors)."""
+           workspace=None, stream=None, check_steps_per_wave: int = 0, variable_chunk: int = 0) -> DecodeOutput:
+    """Decode llr float32 [B, N] against syn uint8 [B, M] (device tensors).
+
+    check_steps_per_wave and variable_chunk (0 = default) select launch shapes
+    of the check and variable kernels; results do not depend on them."""
     import torch
 
     b = int(llr.shape[0])
@@ -156,13 +169,16 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
     iters = torch.empty(b, dtype=torch.int32, device=dev)
     conv = torch.empty(b, dtype=torch.uint8, device=dev)
     post = torch.empty((b, code.N), dtype=torch.float32, device=dev) if posterior else None
+    tuning = met_tuning()
+    tuning.check_steps_per_wave = int(check_steps_per_wave)
+    tuning.variable_chunk = int(variable_chunk)
     check(
-        lib.met_decode(
+        lib.met_decode_ex(
             code.handle, llr.data_ptr(), syn.data_ptr(), b, int(max_iter),
             MET_FIXED_ITERS if fixed_iters else 0,
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(),
             None if post is None else post.data_ptr(),
-            ctypes.c_void_p(ws_ptr), ws_len, _stream_ptr(stream),
+            ctypes.c_void_p(ws_ptr), ws_len, ctypes.byref(tuning), _stream_ptr(stream),
         )
     )
     return DecodeOutput(bits, iters, conv, post)

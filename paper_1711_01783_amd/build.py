@@ -1,6 +1,9 @@
 """Builds the decoder library ``libmetbp.so`` in-tree for gfx950.
 
-    python -m paper_1711_01783_amd.build
+    python paper_1711_01783_amd/build.py
+
+(Run as a file, not as ``-m``: importing the package loads the library, which
+may be missing or stale before the build.)
 
 hipcc cross-compiles for gfx950 without a GPU.  Packed FP32 instructions are
 disabled for all device code.

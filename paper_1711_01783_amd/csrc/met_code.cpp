@@ -477,3 +477,28 @@ extern "C" int met_code_export(const met_code *c, int32_t *vn, int32_t *cn, int8
   if (etype) std::memcpy(etype, c->et.data(), c->E * sizeof(int8_t));
   return MET_OK;
 }
+
+extern "C" int met_code_classes(const met_code *c, met_check_class *out, int32_t max_entries, int32_t *n) {
+  met::clear_error();
+  if (!c || !out || !n || max_entries < 0) return fail(MET_EINVAL, "met_code_classes: NULL argument");
+  const int32_t k = std::min<int32_t>(max_entries, (int32_t)c->classes.size());
+  std::vector<uint8_t> seen(c->N2);
+  for (int32_t i = 0; i < k; ++i) {
+    const met::CheckClass &cc = c->classes[i];
+    out[i].n_msg = cc.shape == met::kShapeGeneric ? -1 : cc.n_msg;
+    out[i].n_leaf = cc.shape == met::kShapeGeneric ? -1 : cc.n_leaf;
+    out[i].first_check = cc.first_check;
+    out[i].n_checks = cc.n_checks;
+    std::fill(seen.begin(), seen.end(), 0);
+    int64_t touched = 0;
+    const int64_t e0 = c->chk_msg_ptr[cc.first_check], e1 = c->chk_msg_ptr[cc.first_check + cc.n_checks];
+    for (int64_t e = e0; e < e1; ++e)
+      if (!seen[c->edge_msgvn[e]]) {
+        seen[c->edge_msgvn[e]] = 1;
+        ++touched;
+      }
+    out[i].n_msg_vn_touched = touched;
+  }
+  *n = (int32_t)c->classes.size();
+  return MET_OK;
+}

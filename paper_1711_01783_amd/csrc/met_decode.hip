@@ -55,6 +55,9 @@ enum : int32_t {
   F_WEIGHTED = 8,  // scale c2v by a per-(edge type, iteration) weight
 };
 
+// Compile-time modes of the fixed-shape check kernel.
+enum : int { M_FIRST = 0, M_MAIN = 1, M_SPECIAL = 2 };
+
 // phi(x) = ln coth(x/2) = -ln tanh(x/2) for x >= 0; phi(0) = inf, phi(inf) = 0.
 // Two pieces, both evaluated (a select, no divergence):
 //  x < 1:  ln(2/x) + z p(z), z = x^2 -- p approximates (ln coth(x/2) - ln(2/x))/x^2
@@ -78,6 +81,19 @@ __device__ __forceinline__ float phi(float x) {
   return x < 1.0f ? lo : hi;
 }
 
+// Index of the calling wave within its block, as a wave-uniform value (so that
+// per-wave addresses stay in scalar registers and index loads are scalar).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Load from memory that no kernel writes while the current one runs (the
+// adjacency, packed syndromes, decisions of the previous iteration).  Going
+// through the constant address space lets wave-uniform loads use the scalar
+// unit (one fetch per wave, batched into wide scalar loads).
+template <typename T>
+__device__ __forceinline__ T ldro(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 __device__ __forceinline__ float clamp_llr(float x) { return fminf(fmaxf(x, -kLlrMax), kLlrMax); }
 
 __device__ __forceinline__ uint32_t sign_bit(float x) { return __float_as_uint(x) >> 31; }
@@ -96,8 +112,16 @@ __device__ __forceinline__ uint64_t fold(uint64_t b) {
   return r;
 }
 
+// Records frames with an unsatisfied check; one atomic per wave at most, and
+// none once the group's flags already hold these bits.
+__device__ __forceinline__ void flag_unsat(uint64_t *dst, uint64_t f) {
+  if (!f) return;
+  const uint64_t seen = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (f & ~seen) __hip_atomic_fetch_or(dst, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct ClassArgs {
-  int32_t shape, n_msg, n_leaf, block_begin;
+  int32_t shape, n_msg, n_leaf, pad;
   int64_t first_check, n_checks, first_msg, first_leaf;
 };
 
@@ -117,11 +141,10 @@ struct CheckParams {
   const uint64_t *B1in;  // [G][EL] leaf decisions of iteration l-1 (F_TEST)
   uint64_t *B1out;       // [G][EL] leaf decisions of iteration l
   uint64_t *unsat;       // [G] frames with an unsatisfied check (F_TEST)
-  uint64_t *unsat_clear; // [G] buffer to zero for iteration l+1's test
+  uint64_t *unsat_clear; // [G] buffer to zero for iteration l+1's test, or NULL
   const uint64_t *active;
   const float *weights;  // [T][wstride]
-  int32_t wstride, it, flags, items_per_wave, n_classes, G;
-  ClassArgs cls[kMaxClasses];
+  int32_t wstride, it, flags, G;
 };
 
 // Decision of a leaf VN after the check update: c = 1 iff L + c2v < 0, with
@@ -134,101 +157,157 @@ __device__ __forceinline__ uint32_t leaf_bit(uint32_t neg_l, uint32_t neg_c, flo
   return 0u;
 }
 
-struct Lane {
-  int g, w, q;
-  uint64_t act;       // active frames of the group
-  bool lane_act;      // this lane's frame is active
-};
+// Writes the W leaf decisions of one item, keeping the stored bits of frames
+// that are no longer active.
+template <int W>
+__device__ __forceinline__ void store_leaf_word(uint64_t *dst, uint64_t ball, int q, uint64_t act) {
+  const uint64_t chunk = (ball >> (q * W)) & wmask<W>();
+  *dst = (act == wmask<W>()) ? chunk : ((*dst & ~act) | (chunk & act));
+}
 
-// One check with a compile-time shape: NM message edges, NL leaf edges.
-template <int W, int NM, int NL>
-__device__ __forceinline__ void check_fixed(const CheckParams &p, const Lane &L, bool valid, int64_t j,
-                                            int64_t m0, int64_t l0, uint32_t &bad) {
+__device__ __forceinline__ void clear_next_unsat(const CheckParams &p) {
+  if (p.unsat_clear && blockIdx.x == 0 && blockIdx.y == 0)
+    for (int gg = threadIdx.x; gg < p.G; gg += kBlock) p.unsat_clear[gg] = 0ull;
+}
+
+// Check update of one class of checks with a compile-time shape (NM message
+// edges, NL leaf edges per check).  Each wave takes IPW consecutive steps of
+// 64/W checks; all loads of its checks are issued before any arithmetic.
+template <int W, int NM, int NL, int MODE, int IPW>
+__global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, const ClassArgs c) {
   constexpr int D = NM + NL;
-  const int g = L.g, w = L.w;
-  const uint32_t s = (uint32_t)(p.synw[(int64_t)g * p.M + j] >> w) & 1u;
-  const bool first = p.flags & F_FIRST, test = p.flags & F_TEST;
-  float A[D];
-  uint32_t neg = 0, parity = s;
+  constexpr int IPWAVE = 64 / W;
+  clear_next_unsat(p);
+  const int g = blockIdx.y;
+  const uint64_t act = p.active[g];
+  if (act == 0ull) return;
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int w = lane % W, q = lane / W;
+  const bool lane_act = (act >> w) & 1ull;
+  const bool first = MODE == M_FIRST || (MODE == M_SPECIAL && (p.flags & F_FIRST));
+  const bool test = MODE != M_FIRST && (p.flags & F_TEST);
+  const bool post = MODE == M_SPECIAL && (p.flags & F_POST);
+  const bool weighted = MODE == M_SPECIAL && (p.flags & F_WEIGHTED);
+  const int64_t base = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * IPW * IPWAVE;
+  if (W == 64 && base >= c.n_checks) return;
+
+  int64_t item[IPW];
+  bool valid[IPW];
+  float pv[IPW][NM > 0 ? NM : 1], cv[IPW][NM > 0 ? NM : 1], lf[IPW][NL > 0 ? NL : 1];
+  uint64_t sw[IPW], b1[IPW][NL > 0 ? NL : 1];
 #pragma unroll
-  for (int k = 0; k < NM; ++k) {
-    const int64_t e = m0 + k;
-    const int32_t vi = p.edge_msgvn[e];
-    const float pv = p.Pin[((int64_t)g * p.N2 + vi) * W + w];
-    const float c = first ? 0.0f : p.c2v[((int64_t)g * p.E12 + e) * W + w];
-    parity ^= (uint32_t)(pv < 0.0f);
-    const float x = clamp_llr(pv - c);
-    A[k] = phi(fabsf(x));
-    neg |= sign_bit(x) << k;
+  for (int k = 0; k < IPW; ++k) {
+    const int64_t i = base + k * IPWAVE + q;
+    valid[k] = i < c.n_checks;
+    item[k] = valid[k] ? i : 0;
   }
+  // loads: P gathers, c2v rows, leaf inputs, syndrome and previous decisions
 #pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int64_t le = l0 + k;
-    const float f = p.Lphi[((int64_t)g * p.EL + le) * W + w];
-    A[NM + k] = fabsf(f);
-    neg |= sign_bit(f) << (NM + k);
-    if (test) parity ^= (uint32_t)(p.B1in[(int64_t)g * p.EL + le] >> w) & 1u;
+  for (int k = 0; k < IPW; ++k) {
+    const int64_t m0 = c.first_msg + item[k] * NM, l0 = c.first_leaf + item[k] * NL;
+    sw[k] = ldro(p.synw, (int64_t)g * p.M + c.first_check + item[k]);
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const int32_t vi = ldro(p.edge_msgvn, m0 + m);
+      pv[k][m] = p.Pin[((int64_t)g * p.N2 + vi) * W + w];
+      cv[k][m] = first ? 0.0f : p.c2v[((int64_t)g * p.E12 + m0 + m) * W + w];
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      lf[k][l] = p.Lphi[((int64_t)g * p.EL + l0 + l) * W + w];
+      b1[k][l] = test ? ldro(p.B1in, (int64_t)g * p.EL + l0 + l) : 0ull;
+    }
   }
-  if (test) bad |= parity & (uint32_t)(valid && L.lane_act);
-  const uint32_t tot = (__popc(neg) & 1u) ^ s;
-  // leave-one-out sums: S_k = prefix_k + suffix_k
-  float pre[D], suf[D];
-  pre[0] = 0.0f;
+  uint32_t bad = 0;
 #pragma unroll
-  for (int k = 1; k < D; ++k) pre[k] = pre[k - 1] + A[k - 1];
-  suf[D - 1] = 0.0f;
+  for (int k = 0; k < IPW; ++k) {
+    const int64_t m0 = c.first_msg + item[k] * NM, l0 = c.first_leaf + item[k] * NL;
+    const uint32_t s = (uint32_t)(sw[k] >> w) & 1u;
+    float A[D];
+    uint32_t neg = 0, parity = s;
 #pragma unroll
-  for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] + A[k + 1];
-  const bool weighted = p.flags & F_WEIGHTED;
-  const bool store = valid && L.lane_act;
+    for (int m = 0; m < NM; ++m) {
+      parity ^= (uint32_t)(pv[k][m] < 0.0f);
+      const float x = clamp_llr(pv[k][m] - cv[k][m]);
+      A[m] = phi(fabsf(x));
+      neg |= sign_bit(x) << m;
+    }
 #pragma unroll
-  for (int k = 0; k < NM; ++k) {
-    const float mag = phi(pre[k] + suf[k]);
-    float out = ((tot ^ (neg >> k)) & 1u) ? -mag : mag;
-    if (weighted) out *= p.weights[(int64_t)p.edge_type[m0 + k] * p.wstride + (p.it - 1)];
-    if (store) p.c2v[((int64_t)g * p.E12 + m0 + k) * W + w] = out;
+    for (int l = 0; l < NL; ++l) {
+      A[NM + l] = fabsf(lf[k][l]);
+      neg |= sign_bit(lf[k][l]) << (NM + l);
+      parity ^= (uint32_t)(b1[k][l] >> w) & 1u;
+    }
+    if (test) bad |= parity & (uint32_t)(valid[k] && lane_act);
+    const uint32_t tot = (__popc(neg) & 1u) ^ s;
+    float pre[D], suf[D];
+    pre[0] = 0.0f;
+#pragma unroll
+    for (int m = 1; m < D; ++m) pre[m] = pre[m - 1] + A[m - 1];
+    suf[D - 1] = 0.0f;
+#pragma unroll
+    for (int m = D - 2; m >= 0; --m) suf[m] = suf[m + 1] + A[m + 1];
+    const bool store = valid[k] && lane_act;
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      const float mag = phi(pre[m] + suf[m]);
+      float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
+      if (weighted) out *= ldro(p.weights, (int64_t)ldro(p.edge_type, m0 + m) * p.wstride + (p.it - 1));
+      if (store) p.c2v[((int64_t)g * p.E12 + m0 + m) * W + w] = out;
+    }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int64_t le = l0 + l;
+      const float S = pre[NM + l] + suf[NM + l];
+      const uint32_t neg_l = (neg >> (NM + l)) & 1u;
+      const uint32_t neg_c = (tot ^ neg_l) & 1u;
+      float wt = 1.0f;
+      if (weighted) wt = ldro(p.weights, (int64_t)ldro(p.leaf_type, le) * p.wstride + (p.it - 1));
+      uint32_t bit;
+      if (wt == 1.0f) {
+        bit = leaf_bit(neg_l, neg_c, S, A[NM + l]);
+      } else {
+        const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
+        const float mag = phi(S);
+        bit = (uint32_t)(lr + wt * (neg_c ? -mag : mag) < 0.0f);
+      }
+      if (post && store) {
+        const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
+        const float mag = phi(S);
+        p.P1[((int64_t)g * p.EL + le) * W + w] = lr + wt * (neg_c ? -mag : mag);
+      }
+      const uint64_t ball = __ballot((int)(bit & (uint32_t)valid[k]));
+      if (w == 0 && valid[k]) store_leaf_word<W>(p.B1out + (int64_t)g * p.EL + le, ball, q, act);
+    }
   }
-#pragma unroll
-  for (int k = 0; k < NL; ++k) {
-    const int64_t le = l0 + k;
-    const float S = pre[NM + k] + suf[NM + k];
-    const uint32_t neg_l = (neg >> (NM + k)) & 1u;
-    const uint32_t neg_c = (tot ^ neg_l) & 1u;
-    uint32_t bit;
-    float wt = 1.0f;
-    if (weighted) wt = p.weights[(int64_t)p.leaf_type[le] * p.wstride + (p.it - 1)];
-    if (wt == 1.0f) {
-      bit = leaf_bit(neg_l, neg_c, S, A[NM + k]);
-    } else {
-      const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
-      const float mag = phi(S);
-      bit = (uint32_t)(lr + wt * (neg_c ? -mag : mag) < 0.0f);
-    }
-    if (p.flags & F_POST) {
-      const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
-      const float mag = phi(S);
-      if (store) p.P1[((int64_t)g * p.EL + le) * W + w] = lr + wt * (neg_c ? -mag : mag);
-    }
-    const uint64_t ball = __ballot((int)(bit & (uint32_t)valid));
-    if (L.w == 0 && valid) {
-      const uint64_t chunk = (ball >> (L.q * W)) & wmask<W>();
-      uint64_t *dst = p.B1out + (int64_t)g * p.EL + le;
-      *dst = (L.act == wmask<W>()) ? chunk : ((*dst & ~L.act) | (chunk & L.act));
-    }
+  if (test) {
+    const uint64_t f = fold<W>(__ballot((int)bad));
+    if (lane == 0) flag_unsat(p.unsat + g, f);
   }
 }
 
-// One check with run-time degrees (total degree <= MET_MAX_CHECK_DEGREE).
+// Check update with run-time degrees (total degree <= MET_MAX_CHECK_DEGREE),
+// for classes without a compiled shape.  One check per lane group.
 template <int W>
-__device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &L, bool valid, int64_t j,
-                                              uint32_t &bad) {
+__global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, const ClassArgs c) {
   constexpr int D = MET_MAX_CHECK_DEGREE;
-  const int g = L.g, w = L.w;
+  clear_next_unsat(p);
+  const int g = blockIdx.y;
+  const uint64_t act = p.active[g];
+  if (act == 0ull) return;
+  const int lane = threadIdx.x & 63, wv = wave_id();
+  const int w = lane % W, q = lane / W;
+  const bool lane_act = (act >> w) & 1ull;
+  const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * (64 / W) + q;
+  if (W == 64 && i >= c.n_checks) return;
+  const bool valid = i < c.n_checks;
+  const int64_t j = c.first_check + (valid ? i : 0);
+  const bool first = p.flags & F_FIRST, test = p.flags & F_TEST;
+  const bool weighted = p.flags & F_WEIGHTED;
   const int64_t m0 = p.chk_msg_ptr[j], l0 = p.chk_leaf_ptr[j];
   const int nm = p.chk_msg_ptr[j + 1] - (int32_t)m0;
   const int nl = p.chk_leaf_ptr[j + 1] - (int32_t)l0;
   const uint32_t s = (uint32_t)(p.synw[(int64_t)g * p.M + j] >> w) & 1u;
-  const bool first = p.flags & F_FIRST, test = p.flags & F_TEST;
   float A[D];
   uint32_t neg = 0, parity = s;
 #pragma unroll
@@ -237,9 +316,9 @@ __device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &
     if (k < nm) {
       const int64_t e = m0 + k;
       const float pv = p.Pin[((int64_t)g * p.N2 + p.edge_msgvn[e]) * W + w];
-      const float c = first ? 0.0f : p.c2v[((int64_t)g * p.E12 + e) * W + w];
+      const float cv = first ? 0.0f : p.c2v[((int64_t)g * p.E12 + e) * W + w];
       parity ^= (uint32_t)(pv < 0.0f);
-      const float x = clamp_llr(pv - c);
+      const float x = clamp_llr(pv - cv);
       A[k] = phi(fabsf(x));
       neg |= sign_bit(x) << k;
     } else if (k < nm + nl) {
@@ -250,7 +329,7 @@ __device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &
       if (test) parity ^= (uint32_t)(p.B1in[(int64_t)g * p.EL + le] >> w) & 1u;
     }
   }
-  if (test) bad |= parity & (uint32_t)(valid && L.lane_act);
+  const uint32_t bad = test ? (parity & (uint32_t)(valid && lane_act)) : 0u;
   const uint32_t tot = (__popc(neg) & 1u) ^ s;
   float pre[D], suf[D];
   pre[0] = 0.0f;
@@ -259,8 +338,7 @@ __device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &
   suf[D - 1] = 0.0f;
 #pragma unroll
   for (int k = D - 2; k >= 0; --k) suf[k] = suf[k + 1] + A[k + 1];
-  const bool weighted = p.flags & F_WEIGHTED;
-  const bool store = valid && L.lane_act;
+  const bool store = valid && lane_act;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     if (k < nm) {
@@ -272,7 +350,7 @@ __device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &
   }
   // Leaf decisions: ballots must be executed by every lane of the wave, so the
   // loop runs to the wave-wide maximum leaf count.
-  int nl_max = nl;
+  int nl_max = valid ? nl : 0;
   for (int off = 32; off >= 1; off >>= 1) nl_max = max(nl_max, __shfl_xor(nl_max, off));
   for (int k = 0; k < nl_max; ++k) {
     const bool has = valid && k < nl;
@@ -288,9 +366,9 @@ __device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &
     const uint32_t neg_l = (neg >> (kk & 31)) & 1u;
     const uint32_t neg_c = (tot ^ neg_l) & 1u;
     uint32_t bit = 0;
-    float wt = 1.0f;
     if (has) {
-      if (weighted) wt = p.weights[(int64_t)p.leaf_type[le] * p.wstride + (p.it - 1)];
+      float wt = 1.0f;
+      if (weighted) wt = ldro(p.weights, (int64_t)ldro(p.leaf_type, le) * p.wstride + (p.it - 1));
       if (wt == 1.0f) {
         bit = leaf_bit(neg_l, neg_c, S, Aleaf);
       } else {
@@ -305,79 +383,11 @@ __device__ __forceinline__ void check_generic(const CheckParams &p, const Lane &
       }
     }
     const uint64_t ball = __ballot((int)bit);
-    if (L.w == 0 && has) {
-      const uint64_t chunk = (ball >> (L.q * W)) & wmask<W>();
-      uint64_t *dst = p.B1out + (int64_t)g * p.EL + le;
-      *dst = (L.act == wmask<W>()) ? chunk : ((*dst & ~L.act) | (chunk & L.act));
-    }
+    if (w == 0 && has) store_leaf_word<W>(p.B1out + (int64_t)g * p.EL + le, ball, q, act);
   }
-}
-
-template <int W, int NM, int NL>
-__device__ __forceinline__ void run_fixed(const CheckParams &p, const ClassArgs &c, const Lane &L, int64_t item0,
-                                          int wv, uint32_t &bad) {
-  constexpr int IPWAVE = 64 / W;  // items per wave step
-  for (int k = 0; k < p.items_per_wave; ++k) {
-    const int64_t item = item0 + ((int64_t)k * kWavesPerBlock + wv) * IPWAVE + L.q;
-    const bool valid = item < c.n_checks;
-    const int64_t it = valid ? item : 0;
-    if (W == 64 && !valid) break;
-    check_fixed<W, NM, NL>(p, L, valid, c.first_check + it, c.first_msg + it * NM, c.first_leaf + it * NL, bad);
-  }
-}
-
-// Check update of all checks of the classes in p.cls; the GENERIC instance
-// handles only run-time-degree classes, the other one only compiled shapes
-// (so the common shapes keep a small register footprint).
-template <int W, bool GENERIC>
-__global__ __launch_bounds__(kBlock) void k_check(const CheckParams p) {
-  const int g = blockIdx.y;
-  if (blockIdx.x == 0 && blockIdx.y == 0 && p.unsat_clear)
-    for (int gg = threadIdx.x; gg < p.G; gg += kBlock) p.unsat_clear[gg] = 0ull;
-  const uint64_t act = p.active[g];
-  if (act == 0ull) return;
-  int ci = 0;
-  while (ci + 1 < p.n_classes && (int)blockIdx.x >= p.cls[ci + 1].block_begin) ++ci;
-  const ClassArgs &c = p.cls[ci];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  Lane L;
-  L.g = g;
-  L.w = lane % W;
-  L.q = lane / W;
-  L.act = act;
-  L.lane_act = (act >> L.w) & 1ull;
-  const int64_t per_block = (int64_t)p.items_per_wave * kWavesPerBlock * (64 / W);
-  const int64_t item0 = (int64_t)(blockIdx.x - c.block_begin) * per_block;
-  uint32_t bad = 0;
-  switch (c.shape) {
-    case 0: run_fixed<W, 3, 1>(p, c, L, item0, wv, bad); break;
-    case 1: run_fixed<W, 2, 1>(p, c, L, item0, wv, bad); break;
-    case 2: run_fixed<W, 4, 1>(p, c, L, item0, wv, bad); break;
-    case 3: run_fixed<W, 12, 0>(p, c, L, item0, wv, bad); break;
-    case 4: run_fixed<W, 11, 0>(p, c, L, item0, wv, bad); break;
-    case 5: run_fixed<W, 13, 0>(p, c, L, item0, wv, bad); break;
-    case 6: run_fixed<W, 6, 0>(p, c, L, item0, wv, bad); break;
-    case 7: run_fixed<W, 5, 0>(p, c, L, item0, wv, bad); break;
-    case 8: run_fixed<W, 7, 0>(p, c, L, item0, wv, bad); break;
-    default: {
-      if (GENERIC) {
-        constexpr int IPWAVE = 64 / W;
-        for (int k = 0; k < p.items_per_wave; ++k) {
-          const int64_t item = item0 + ((int64_t)k * kWavesPerBlock + wv) * IPWAVE + L.q;
-          const bool valid = item < c.n_checks;
-          if (W == 64 && !valid) break;
-          check_generic<W>(p, L, valid, c.first_check + (valid ? item : 0), bad);
-        }
-      }
-    }
-  }
-  if (p.flags & F_TEST) {
+  if (test) {
     const uint64_t f = fold<W>(__ballot((int)bad));
-    if (lane == 0 && f) {
-      uint64_t *dst = p.unsat + g;
-      const uint64_t seen = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (f & ~seen) __hip_atomic_fetch_or(dst, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (lane == 0) flag_unsat(p.unsat + g, f);
   }
 }
 
@@ -397,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_test(const TestParams p) {
   const uint64_t act = p.active[g];
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, w = lane % W, q = lane / W;
-  const int64_t j = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * (64 / W) + q;
+  const int64_t j = ((int64_t)blockIdx.x * kWavesPerBlock + wave_id()) * (64 / W) + q;
   uint32_t bad = 0;
   if (j < p.M) {
     uint32_t parity = (uint32_t)(p.synw[(int64_t)g * p.M + j] >> w) & 1u;
@@ -408,11 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_test(const TestParams p) {
     bad = parity & (uint32_t)((act >> w) & 1ull);
   }
   const uint64_t f = fold<W>(__ballot((int)bad));
-  if (lane == 0 && f) {
-    uint64_t *dst = p.unsat + g;
-    const uint64_t seen = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (f & ~seen) __hip_atomic_fetch_or(dst, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (lane == 0) flag_unsat(p.unsat + g, f);
 }
 
 struct VarParams {
@@ -425,10 +431,12 @@ struct VarParams {
   const uint64_t *unsat; // [G] test result of iteration it-1 (retire mode)
   int32_t *iters;
   uint8_t *converged;
-  int32_t it, retire, items_per_wave, G, B;
+  int32_t it, retire, G;
 };
 
-template <int W>
+// Variable update: P_v = L_v + sum of c2v over v's message edges (gathered U
+// at a time, summed in list order).
+template <int W, int U>
 __global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
   const int g = blockIdx.y;
   uint64_t act = p.active[g];
@@ -453,30 +461,31 @@ __global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
     act &= p.unsat[g];
   }
   if (act == 0ull) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, w = lane % W, q = lane / W;
+  const int lane = threadIdx.x & 63, wv = wave_id(), w = lane % W, q = lane / W;
   const bool lane_act = (act >> w) & 1ull;
-  const int64_t per_block = (int64_t)p.items_per_wave * kWavesPerBlock * (64 / W);
-  const int64_t base = (int64_t)blockIdx.x * per_block;
-  for (int k = 0; k < p.items_per_wave; ++k) {
-    const int64_t i = base + ((int64_t)k * kWavesPerBlock + wv) * (64 / W) + q;
-    if (i >= p.N2) break;
-    const int32_t e0 = p.vn_ptr[i], e1 = p.vn_ptr[i + 1];
-    float P = p.L2[((int64_t)g * p.N2 + i) * W + w];
-    const float *c2v = p.c2v + (int64_t)g * p.E12 * W + w;
-    int32_t e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const float a0 = c2v[(int64_t)p.vn_edges[e] * W];
-      const float a1 = c2v[(int64_t)p.vn_edges[e + 1] * W];
-      const float a2 = c2v[(int64_t)p.vn_edges[e + 2] * W];
-      const float a3 = c2v[(int64_t)p.vn_edges[e + 3] * W];
-      P += a0;
-      P += a1;
-      P += a2;
-      P += a3;
-    }
-    for (; e < e1; ++e) P += c2v[(int64_t)p.vn_edges[e] * W];
-    if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
+  const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * (64 / W) + q;
+  if (i >= p.N2) return;
+  const int32_t e0 = ldro(p.vn_ptr, i), e1 = ldro(p.vn_ptr, i + 1);
+  float P = p.L2[((int64_t)g * p.N2 + i) * W + w];
+  const float *c2v = p.c2v + (int64_t)g * p.E12 * W + w;
+  int32_t e = e0;
+  for (; e + U <= e1; e += U) {
+    float a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
+#pragma unroll
+    for (int u = 0; u < U; ++u) P += a[u];
   }
+  if (U > 8)
+    for (; e + 8 <= e1; e += 8) {
+      float a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) P += a[u];
+    }
+  for (; e < e1; ++e) P += c2v[(int64_t)ldro(p.vn_edges, e) * W];
+  if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
 }
 
 // ----------------------------------------------------------------------------
@@ -495,17 +504,22 @@ struct InitParams {
   uint8_t *converged;
 };
 
-// llr [B][N] -> Lt [G][N][W]; lanes run along N so every row read is coalesced.
+// llr [B][N] -> Lt [G][N][W] through an LDS tile of 64 VNs x W frames: reads
+// are rows of 64 consecutive VNs, writes are W*64 consecutive floats.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_transpose(const InitParams p) {
+  __shared__ float tile[W][65];
   const int g = blockIdx.y;
-  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (v >= p.N) return;
-  float *dst = p.Lt + ((int64_t)g * p.N + v) * W;
-#pragma unroll 8
-  for (int w = 0; w < W; ++w) {
-    const int f = g * W + w;
-    dst[w] = f < p.B ? p.llr[(int64_t)f * p.N + v] : 0.0f;
+  const int64_t v0 = (int64_t)blockIdx.x * 64;
+  for (int idx = threadIdx.x; idx < W * 64; idx += kBlock) {
+    const int f = idx / 64, v = idx % 64;
+    const int frame = g * W + f;
+    tile[f][v] = (frame < p.B && v0 + v < p.N) ? p.llr[(int64_t)frame * p.N + v0 + v] : 0.0f;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W * 64; idx += kBlock) {
+    const int v = idx / W, f = idx % W;
+    if (v0 + v < p.N) p.Lt[((int64_t)g * p.N + v0 + v) * W + f] = tile[f][v];
   }
 }
 
@@ -576,26 +590,46 @@ __global__ void k_final_status(const FinalParams p) {
   }
 }
 
+// Outputs in user order through an LDS tile of 64 VNs x W frames: reads are
+// item rows of W frames, writes are runs of 64 consecutive VNs per frame.
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_finalize(const FinalParams p) {
-  const int f = blockIdx.y;
-  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (v >= p.N) return;
-  const int g = f / W, w = f % W;
-  const int32_t slot = p.vn_slot[v];
-  const bool odd = p.iters[f] & 1;
-  uint8_t bit;
-  float post = 0.0f;
-  if (slot >= 0) {
-    post = p.P[((int64_t)g * p.N2 + slot) * W + w];
-    bit = post < 0.0f;
-  } else {
-    const int64_t le = -(int64_t)slot - 1;
-    bit = (uint8_t)(((odd ? p.B1b : p.B1a)[(int64_t)g * p.EL + le] >> w) & 1ull);
-    if (p.posterior) post = (odd ? p.P1b : p.P1a)[((int64_t)g * p.EL + le) * W + w];
+  __shared__ float val[64][W + 1];
+  __shared__ uint8_t bit[64][W + 1];
+  __shared__ uint8_t odd[W];
+  const int g = blockIdx.y;
+  const int64_t v0 = (int64_t)blockIdx.x * 64;
+  if (threadIdx.x < W) {
+    const int f = g * W + threadIdx.x;
+    odd[threadIdx.x] = f < p.B ? (uint8_t)(p.iters[f] & 1) : 0;
   }
-  p.bits[(int64_t)f * p.N + v] = bit;
-  if (p.posterior) p.posterior[(int64_t)f * p.N + v] = post;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W * 64; idx += kBlock) {
+    const int v = idx / W, w = idx % W;
+    float post = 0.0f;
+    uint8_t b = 0;
+    if (v0 + v < p.N) {
+      const int32_t slot = p.vn_slot[v0 + v];
+      if (slot >= 0) {
+        post = p.P[((int64_t)g * p.N2 + slot) * W + w];
+        b = post < 0.0f;
+      } else {
+        const int64_t le = -(int64_t)slot - 1;
+        b = (uint8_t)(((odd[w] ? p.B1b : p.B1a)[(int64_t)g * p.EL + le] >> w) & 1ull);
+        if (p.posterior) post = (odd[w] ? p.P1b : p.P1a)[((int64_t)g * p.EL + le) * W + w];
+      }
+    }
+    val[v][w] = post;
+    bit[v][w] = b;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W * 64; idx += kBlock) {
+    const int w = idx / 64, v = idx % 64;
+    const int f = g * W + w;
+    if (f >= p.B || v0 + v >= p.N) continue;
+    p.bits[(int64_t)f * p.N + v0 + v] = bit[v][w];
+    if (p.posterior) p.posterior[(int64_t)f * p.N + v0 + v] = val[v][w];
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_syndrome(const int32_t *all_vn, const int32_t *all_ptr, int64_t N,
@@ -662,10 +696,12 @@ struct Plan {
   bool lraw = false, p1 = false;
 };
 
+// Frames per group: the smallest supported width that holds min(B, 64).
 int choose_interleave(int B) {
-  int W = 1;
-  while (W < B && W < 64) W <<= 1;
-  return W;
+  if (B <= 1) return 1;
+  if (B <= 4) return 4;
+  if (B <= 16) return 16;
+  return 64;
 }
 
 Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
@@ -702,6 +738,37 @@ Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
     if (e_ != hipSuccess) return fail(MET_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+template <int W, int MODE, int IPW>
+void launch_fixed(int shape, unsigned blocks, int G, hipStream_t st, const CheckParams &p, const ClassArgs &c) {
+  const dim3 grid(blocks, G), block(kBlock);
+  switch (shape) {
+    case 0: hipLaunchKernelGGL((k_check_fixed<W, 3, 1, MODE, IPW>), grid, block, 0, st, p, c); break;
+    case 1: hipLaunchKernelGGL((k_check_fixed<W, 2, 1, MODE, IPW>), grid, block, 0, st, p, c); break;
+    case 2: hipLaunchKernelGGL((k_check_fixed<W, 12, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+    case 3: hipLaunchKernelGGL((k_check_fixed<W, 11, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+    case 4: hipLaunchKernelGGL((k_check_fixed<W, 6, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+    default: hipLaunchKernelGGL((k_check_fixed<W, 5, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+  }
+}
+
+template <int W, int MODE>
+void launch_fixed_ipw(int ipw, int shape, unsigned blocks, int G, hipStream_t st, const CheckParams &p,
+                      const ClassArgs &c) {
+  if (W == 64 && ipw == 4)
+    launch_fixed<W, MODE, (W == 64 ? 4 : 1)>(shape, blocks, G, st, p, c);
+  else if (W == 64 && ipw == 2)
+    launch_fixed<W, MODE, (W == 64 ? 2 : 1)>(shape, blocks, G, st, p, c);
+  else
+    launch_fixed<W, MODE, 1>(shape, blocks, G, st, p, c);
+}
+
+// Timer names of the check kernels, by shape.
+const char *const kCheckKernelName[kNumFixedShapes + 1] = {
+    "k_check<3,1>", "k_check<2,1>", "k_check<12,0>", "k_check<11,0>", "k_check<6,0>", "k_check<5,0>",
+    "k_check_generic"};
+static_assert(kShapeMsg[0] == 3 && kShapeLeaf[0] == 1 && kShapeMsg[2] == 12 && kShapeMsg[5] == 5,
+              "timer names follow the shape table");
+
 struct Decoder {
   const met_code *c;
   const DeviceCode *d;
@@ -709,10 +776,27 @@ struct Decoder {
   char *ws;
   hipStream_t st;
   int B;
-  int cn_ipw = 2, vn_ipw = 1;
+  int cn_ipw = 4;    // check steps per wave (W = 64 only): 1, 2 or 4
+  int vn_chunk = 16; // gathers in flight per variable node: 8, 16 or 32
 
   template <typename T>
   T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+
+  template <int W>
+  void check_launch(const CheckParams &p, const ClassArgs &a, int mode) {
+    const bool gen = a.shape == kShapeGeneric;
+    const int ipw = (W == 64 && !gen && mode != M_SPECIAL) ? cn_ipw : 1;
+    const int64_t per_block = (int64_t)kWavesPerBlock * ipw * (64 / W);
+    const unsigned blocks = (unsigned)((a.n_checks + per_block - 1) / per_block);
+    if (gen)
+      hipLaunchKernelGGL(k_check_generic<W>, dim3(blocks, pl.G), dim3(kBlock), 0, st, p, a);
+    else if (mode == M_SPECIAL)
+      launch_fixed<W, M_SPECIAL, 1>(a.shape, blocks, pl.G, st, p, a);
+    else if (mode == M_FIRST)
+      launch_fixed_ipw<W, M_FIRST>(ipw, a.shape, blocks, pl.G, st, p, a);
+    else
+      launch_fixed_ipw<W, M_MAIN>(ipw, a.shape, blocks, pl.G, st, p, a);
+  }
 
   template <int W>
   int run(const float *llr, const uint8_t *syn, int max_iter, uint32_t flags, uint8_t *bits, int32_t *iters,
@@ -749,7 +833,7 @@ struct Decoder {
     ip.converged = conv;
     {
       ScopedTimer t(st, "k_transpose");
-      hipLaunchKernelGGL(k_transpose<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st, ip);
+      hipLaunchKernelGGL(k_transpose<W>, dim3((unsigned)((c->N + 63) / 64), G), dim3(kBlock), 0, st, ip);
     }
     {
       const int64_t n = (c->N2 + c->EL) * W;
@@ -780,19 +864,10 @@ struct Decoder {
     cp.active = active;
     cp.weights = weights;
     cp.wstride = wstride;
-    cp.items_per_wave = cn_ipw;
     cp.G = G;
-    // Fixed-shape classes go to one launch, run-time-degree classes to another.
-    CheckParams gp = cp;
-    int cn_blocks = 0, gen_blocks = 0;
-    cp.n_classes = 0;
-    gp.n_classes = 0;
-    const int64_t per_block = (int64_t)cn_ipw * kWavesPerBlock * (64 / W);
+    std::vector<ClassArgs> classes;
     for (const CheckClass &cc : c->classes) {
-      const bool gen = cc.shape == kShapeGeneric;
-      CheckParams &dst = gen ? gp : cp;
-      int &blocks = gen ? gen_blocks : cn_blocks;
-      ClassArgs &a = dst.cls[dst.n_classes++];
+      ClassArgs a{};
       a.shape = cc.shape;
       a.n_msg = cc.n_msg;
       a.n_leaf = cc.n_leaf;
@@ -800,8 +875,7 @@ struct Decoder {
       a.n_checks = cc.n_checks;
       a.first_msg = cc.first_msg;
       a.first_leaf = cc.first_leaf;
-      a.block_begin = blocks;
-      blocks += (int)((cc.n_checks + per_block - 1) / per_block);
+      classes.push_back(a);
     }
     VarParams vp{};
     vp.vn_ptr = d->vn_ptr;
@@ -814,12 +888,11 @@ struct Decoder {
     vp.active = active;
     vp.iters = iters;
     vp.converged = conv;
-    vp.items_per_wave = vn_ipw;
     vp.G = G;
-    vp.B = B;
-    const int64_t vn_per_block = (int64_t)vn_ipw * kWavesPerBlock * (64 / W);
+    const int64_t vn_per_block = (int64_t)kWavesPerBlock * (64 / W);
     const unsigned vn_blocks = (unsigned)((c->N2 + vn_per_block - 1) / vn_per_block);
     const bool early = !(flags & MET_FIXED_ITERS);
+    const bool special = post || weights;
     const int base_flags = (post ? F_POST : 0) | (weights ? F_WEIGHTED : 0);
 
     for (int it = 1; it <= max_iter; ++it) {
@@ -830,29 +903,24 @@ struct Decoder {
       cp.B1out = B1 + (size_t)(it & 1) * leaf_words;
       cp.P1 = P1 ? P1 + (size_t)(it & 1) * leaf_floats : nullptr;
       cp.unsat = unsat + (size_t)((it - 1) & 1) * G;
-      cp.unsat_clear = unsat + (size_t)(it & 1) * G;
-      if (cn_blocks > 0) {
-        ScopedTimer t(st, "k_check");
-        hipLaunchKernelGGL((k_check<W, false>), dim3(cn_blocks, G), dim3(kBlock), 0, st, cp);
-      }
-      if (gen_blocks > 0) {
-        ScopedTimer t(st, "k_check_generic");
-        gp.it = cp.it;
-        gp.flags = cp.flags;
-        gp.Pin = cp.Pin;
-        gp.B1in = cp.B1in;
-        gp.B1out = cp.B1out;
-        gp.P1 = cp.P1;
-        gp.unsat = cp.unsat;
-        gp.unsat_clear = cn_blocks > 0 ? nullptr : cp.unsat_clear;
-        hipLaunchKernelGGL((k_check<W, true>), dim3(gen_blocks, G), dim3(kBlock), 0, st, gp);
+      const int mode = special ? M_SPECIAL : (it == 1 ? M_FIRST : M_MAIN);
+      for (size_t k = 0; k < classes.size(); ++k) {
+        cp.unsat_clear = k == 0 ? unsat + (size_t)(it & 1) * G : nullptr;
+        ScopedTimer t(st, kCheckKernelName[classes[k].shape]);
+        check_launch<W>(cp, classes[k], mode);
       }
       vp.it = it;
       vp.retire = early && it >= 2;
       vp.unsat = unsat + (size_t)((it - 1) & 1) * G;
       if (vn_blocks > 0) {
         ScopedTimer t(st, "k_variable");
-        hipLaunchKernelGGL(k_variable<W>, dim3(vn_blocks, G), dim3(kBlock), 0, st, vp);
+        const dim3 grid(vn_blocks, G);
+        if (vn_chunk == 32)
+          hipLaunchKernelGGL((k_variable<W, 32>), grid, dim3(kBlock), 0, st, vp);
+        else if (vn_chunk == 16)
+          hipLaunchKernelGGL((k_variable<W, 16>), grid, dim3(kBlock), 0, st, vp);
+        else
+          hipLaunchKernelGGL((k_variable<W, 8>), grid, dim3(kBlock), 0, st, vp);
       }
     }
     TestParams tp{};
@@ -895,7 +963,7 @@ struct Decoder {
     {
       ScopedTimer t(st, "k_finalize");
       hipLaunchKernelGGL(k_final_status<W>, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fp);
-      hipLaunchKernelGGL(k_finalize<W>, dim3((unsigned)((c->N + kBlock - 1) / kBlock), B), dim3(kBlock), 0, st, fp);
+      hipLaunchKernelGGL(k_finalize<W>, dim3((unsigned)((c->N + 63) / 64), G), dim3(kBlock), 0, st, fp);
     }
     HIP_TRY(hipGetLastError());
     return MET_OK;
@@ -1011,9 +1079,9 @@ extern "C" int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t
   return MET_OK;
 }
 
-extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
-                          uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
-                          void *workspace, size_t ws_bytes, void *stream) {
+extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
+                             uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
+                             void *workspace, size_t ws_bytes, const met_tuning *tuning, void *stream) {
   met::clear_error();
   int rc = validate_decode(c, B, flags);
   if (rc) return rc;
@@ -1022,22 +1090,37 @@ extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *sy
   if (((uintptr_t)llr & 3) || ((uintptr_t)posterior & 3) || ((uintptr_t)iters & 3))
     return fail(MET_EINVAL, "misaligned float/int buffer");
   if ((uintptr_t)workspace & 255) return fail(MET_EINVAL, "workspace must be 256-byte aligned");
+  int ipw = 4, chunk = 16;
+  if (tuning) {
+    const int s = tuning->check_steps_per_wave;
+    if (s != 0 && s != 1 && s != 2 && s != 4) return fail(MET_EINVAL, "check_steps_per_wave must be 0, 1, 2 or 4");
+    if (s) ipw = s;
+    const int u = tuning->variable_chunk;
+    if (u != 0 && u != 8 && u != 16 && u != 32) return fail(MET_EINVAL, "variable_chunk must be 0, 8, 16 or 32");
+    if (u) chunk = u;
+    for (int r = 0; r < 6; ++r)
+      if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
+  }
   const int W = met::choose_interleave(B);
   const met::Plan pl = met::make_plan(c, B, posterior != nullptr, false, W);
   if (ws_bytes < pl.total) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, pl.total);
   const met::DeviceCode *d = nullptr;
   rc = met::device_code(c, &d);
   if (rc) return rc;
-  met::Decoder dec{c, d, pl, static_cast<char *>(workspace), (hipStream_t)stream, B};
+  met::Decoder dec{c, d, pl, static_cast<char *>(workspace), (hipStream_t)stream, B, ipw, chunk};
   switch (W) {
     case 1: return dec.run<1>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
-    case 2: return dec.run<2>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     case 4: return dec.run<4>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
-    case 8: return dec.run<8>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     case 16: return dec.run<16>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
-    case 32: return dec.run<32>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     default: return dec.run<64>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   }
+}
+
+extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
+                          uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
+                          void *workspace, size_t ws_bytes, void *stream) {
+  return met_decode_ex(c, llr, syn, B, max_iter, flags, bits, iters, converged, posterior, workspace, ws_bytes,
+                       nullptr, stream);
 }
 
 extern "C" int met_timing_enable(int32_t on) {

@@ -18,9 +18,9 @@ void clear_error();
 // check.  "Message" edges go to variable nodes of degree >= 2; "leaf" edges go
 // to degree-1 variable nodes, whose variable-to-check message is always the
 // channel LLR and which therefore never enter the iterations.
-constexpr int kNumFixedShapes = 9;
-constexpr int kShapeMsg[kNumFixedShapes] = {3, 2, 4, 12, 11, 13, 6, 5, 7};
-constexpr int kShapeLeaf[kNumFixedShapes] = {1, 1, 1, 0, 0, 0, 0, 0, 0};
+constexpr int kNumFixedShapes = 6;
+constexpr int kShapeMsg[kNumFixedShapes] = {3, 2, 12, 11, 6, 5};
+constexpr int kShapeLeaf[kNumFixedShapes] = {1, 1, 0, 0, 0, 0};
 constexpr int kShapeGeneric = kNumFixedShapes;  // per-check row pointers
 
 constexpr int kMaxClasses = 16;
