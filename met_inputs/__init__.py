@@ -92,7 +92,7 @@ BJ_SNR = {"r0.1": 0.157, "r0.05": 0.0757, "r0.02": 0.0296}
 ITER_BUDGET = {"r0.1": 100, "r0.05": 150, "r0.02": 200}
 # Points in the waterfall region of these profiles at moderate length, where the
 # frame error rate is strictly between 0 and 1 (chosen with the oracle).
-WATERFALL_SNR = {"r0.1": 0.205, "r0.05": 0.105, "r0.02": 0.068}
+WATERFALL_SNR = {"r0.1": 0.19, "r0.05": 0.10, "r0.02": 0.065}
 
 
 def beta_efficiency(rate: float, snr: float) -> float:

@@ -1,0 +1,81 @@
+"""Writes the oracle's per-frame outcomes used by the GPU FER-parity test.
+
+    python tests/golden/make_fer_golden.py [--frames 1024] [--workers 8]
+
+Calls only the FP64 oracle (`oracle/`) and the seeded input module
+(`met_inputs`).  For each rate: the code built by `oracle.code.build` from the
+profile with CODE_SEED, N = 65536, frames FRAME_SEED + f at the waterfall SNR,
+decoded in early-exit mode with the rate's iteration budget.  Stored per frame:
+converged flag, iterations, frame error (decoded bits != sent bits) and the
+SHA-1 of the decoded bits.
+"""
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from met_inputs import ITER_BUDGET, PROFILES, WATERFALL_SNR, make_frames  # noqa: E402
+from oracle import bp, code as oc  # noqa: E402
+
+N = 65536
+CODE_SEED = 31
+FRAME_SEED = 90000
+CHUNK = 16
+_CODE = {}
+
+
+def _work(args):
+    prof, f0, nf = args
+    code = _CODE[prof]
+    bits, llr = make_frames(N, nf, WATERFALL_SNR[prof], FRAME_SEED, first_frame=f0)
+    syn = oc.syndrome(code, bits)
+    r = bp.decode(code, llr, syn, ITER_BUDGET[prof])
+    out = []
+    for i in range(nf):
+        out.append({
+            "frame": f0 + i,
+            "converged": int(r.converged[i]),
+            "iterations": int(r.iterations[i]),
+            "frame_error": int(np.any(r.bits[i] != bits[i])),
+            "bits_sha1": hashlib.sha1(r.bits[i].tobytes()).hexdigest(),
+        })
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=1024)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--rates", default="r0.1,r0.05,r0.02")
+    args = ap.parse_args()
+    for prof in args.rates.split(","):
+        _CODE[prof] = oc.build(PROFILES[prof], N, CODE_SEED)
+        jobs = [(prof, f0, min(CHUNK, args.frames - f0)) for f0 in range(0, args.frames, CHUNK)]
+        with mp.get_context("fork").Pool(args.workers) as pool:
+            frames = [x for part in pool.map(_work, jobs) for x in part]
+        rec = {
+            "source": "oracle/bp.py early-exit decode; tests/golden/make_fer_golden.py",
+            "profile": prof,
+            "N": N,
+            "code_seed": CODE_SEED,
+            "frame_seed": FRAME_SEED,
+            "snr": WATERFALL_SNR[prof],
+            "max_iter": ITER_BUDGET[prof],
+            "frames": frames,
+        }
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fer_%s_N%d.json" % (prof, N))
+        with open(path, "w") as f:
+            json.dump(rec, f, separators=(",", ":"))
+        fer = sum(x["frame_error"] for x in frames) / len(frames)
+        print(prof, "FER", fer, "converged", sum(x["converged"] for x in frames), "->", path, flush=True)
+
+
+if __name__ == "__main__":
+    main()
