@@ -182,6 +182,37 @@ typedef struct {
 int met_timing_enable(int32_t on);
 int met_timing_collect(met_kernel_time *out, int32_t max_entries, int32_t *n_entries);
 
+/* ---- Weighted BP (learnable message scales) ------------------------------
+ * The decoder above run for a fixed number of iterations L, with the
+ * check-to-variable message of every edge of type t produced in iteration l
+ * multiplied by weights[t * L + (l - 1)] after the syndrome sign (Step 3) and
+ * before the variable update (Step 4).  weights = 1 gives exactly met_decode's
+ * fixed-iteration results.  The forward pass keeps the message state of every
+ * ckpt_every-th iteration in the workspace; the backward pass recomputes the
+ * iterations between checkpoints and runs hand-written adjoint kernels in
+ * reverse.  Irregular (non-compiled) check shapes must have degree <= 16. */
+
+/* Workspace bytes for forward + backward (B frames, L iterations, a checkpoint
+ * every ckpt_every iterations).  Errors: MET_EINVAL. */
+int met_wbp_workspace_bytes(const met_code *c, int32_t B, int32_t iterations, int32_t ckpt_every, size_t *bytes);
+
+/* Forward pass.  llr dev f32 [B][N], syn dev u8 [B][M], weights dev f32
+ * [n_edge_types][iterations]; outputs posterior dev f32 [B][N] (after the last
+ * iteration, eq. (5)), and optionally bits dev u8 [B][N] and converged dev u8
+ * [B] (may be NULL).  The workspace (256-byte aligned, uninitialised) must be
+ * passed unchanged to met_wbp_backward.  Errors: MET_EINVAL, MET_EHIP. */
+int met_wbp_forward(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t iterations,
+                    const float *weights, int32_t ckpt_every, float *posterior, uint8_t *bits,
+                    uint8_t *converged, void *workspace, size_t ws_bytes, void *stream);
+
+/* Backward pass: grad_posterior dev f32 [B][N] (dLoss/dposterior) ->
+ * grad_weights dev f32 [n_edge_types][iterations] (overwritten).  Same code,
+ * B, iterations, weights, ckpt_every and workspace as the forward call.
+ * Deterministic (fixed reduction order).  Errors: MET_EINVAL, MET_EHIP. */
+int met_wbp_backward(const met_code *c, const float *grad_posterior, int32_t B, int32_t iterations,
+                     const float *weights, int32_t ckpt_every, float *grad_weights, void *workspace,
+                     size_t ws_bytes, void *stream);
+
 /* Launch-shape choices for met_decode_ex; 0 in a field selects the default. */
 typedef struct {
   int32_t check_steps_per_wave; /* 1, 2 or 4: steps of 64/W checks each wave of

@@ -89,6 +89,9 @@ def _load():
         "met_decode": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, P]),
         "met_last_error": (ctypes.c_char_p, []),
         "met_decode_ex": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, ctypes.POINTER(met_tuning), P]),
+        "met_wbp_workspace_bytes": (ctypes.c_int, [P, i32, i32, i32, ctypes.POINTER(sz)]),
+        "met_wbp_forward": (ctypes.c_int, [P, P, P, i32, i32, P, i32, P, P, P, P, sz, P]),
+        "met_wbp_backward": (ctypes.c_int, [P, P, i32, i32, P, i32, P, P, sz, P]),
         "met_timing_enable": (ctypes.c_int, [i32]),
         "met_timing_collect": (ctypes.c_int, [ctypes.POINTER(met_kernel_time), i32, ctypes.POINTER(i32)]),
     }
