@@ -213,14 +213,21 @@ int met_wbp_backward(const met_code *c, const float *grad_posterior, int32_t B, 
                      const float *weights, int32_t ckpt_every, float *grad_weights, void *workspace,
                      size_t ws_bytes, void *stream);
 
-/* Launch-shape choices for met_decode_ex; 0 in a field selects the default. */
+/* Launch-shape choices for met_decode_ex and met_decode_batched; 0 in a field
+ * selects the default. */
+#define MET_BATCH_NO_STAGGER 1u /* batched: all jobs start in the same phase */
+#define MET_BATCH_NO_GRAPH 2u   /* batched: plain launches instead of a HIP graph */
+
 typedef struct {
   int32_t check_steps_per_wave; /* 1, 2 or 4: steps of 64/W checks each wave of
                                    the check kernel loads before computing
                                    (groups of 64 frames only); default 4 */
   int32_t variable_chunk;       /* 8, 16 or 32: message gathers the variable
                                    kernel keeps in flight; default 16 */
-  int32_t reserved[6];          /* must be 0 */
+  int32_t blocks_per_cu;        /* batched: resident blocks per compute unit
+                                   (0 = as many as fit) */
+  uint32_t batch_flags;         /* batched: MET_BATCH_* */
+  int32_t reserved[4];          /* must be 0 */
 } met_tuning;
 
 /* met_decode with explicit launch shapes (tuning may be NULL).  Results do not
@@ -228,6 +235,41 @@ typedef struct {
 int met_decode_ex(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
                   uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
                   void *workspace, size_t ws_bytes, const met_tuning *tuning, void *stream);
+
+/* ---- Batched decoding ------------------------------------------------------
+ * Several decode jobs -- possibly different codes (rates), batch sizes and
+ * iteration budgets -- in one persistent kernel launch whose iterations of all
+ * jobs are interleaved (captured with its set-up and output kernels in one HIP
+ * graph, cached per configuration).  Each job's results are identical to
+ * met_decode's for the same inputs (the same kernels decode them, with groups
+ * of 64 frames).  The launch is persistent: its grid is sized to be resident
+ * at once and steps through the iterations of all jobs with a grid-wide
+ * barrier between phases.  Batches holding codes with check degrees that have
+ * no compiled shape run with one check step per wave. */
+typedef struct {
+  const met_code *code;
+  const float *llr;     /* dev f32 [B][N] */
+  const uint8_t *syn;   /* dev u8 [B][M] */
+  int32_t B, max_iter;
+  uint32_t flags;       /* MET_EARLY_EXIT or MET_FIXED_ITERS */
+  uint8_t *bits;        /* dev u8 [B][N] out */
+  int32_t *iters;       /* dev i32 [B] out */
+  uint8_t *converged;   /* dev u8 [B] out */
+  float *posterior;     /* must be NULL (posteriors: use met_decode) */
+} met_job;
+
+/* Workspace bytes for these jobs.  Errors: MET_EINVAL. */
+int met_batched_workspace_bytes(const met_job *jobs, int32_t n_jobs, size_t *bytes);
+
+/* Enqueues all jobs on `stream` (tuning may be NULL).  The workspace (256-byte
+ * aligned) must not be shared with overlapping calls.  After the stream has
+ * drained, met_batched_check tells whether the persistent launch's barrier
+ * ever expired (which happens only if its blocks were not all resident, e.g.
+ * another process held compute units); results are then invalid.
+ * Errors: MET_EINVAL, MET_EHIP. */
+int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
+                       const met_tuning *tuning, void *stream);
+int met_batched_check(const void *workspace, int32_t *barrier_expired);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *met_last_error(void);

@@ -17,11 +17,16 @@ from ._lib import (
     lib,
     library_path,
 )
-from .api import Code, DecodeOutput, decode, syndrome, timing_collect, timing_enable, workspace_bytes
+from .api import (BatchedDecoder, Code, DecodeOutput, Job, batched_workspace_bytes, decode, decode_batched, syndrome,
+                  timing_collect, timing_enable, workspace_bytes)
 
 __all__ = [
+    "BatchedDecoder",
     "Code",
     "DecodeOutput",
+    "Job",
+    "batched_workspace_bytes",
+    "decode_batched",
     "MET_EARLY_EXIT",
     "MET_FIXED_ITERS",
     "MetError",

@@ -59,9 +59,21 @@ class met_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+MET_BATCH_NO_STAGGER = 1
+MET_BATCH_NO_GRAPH = 2
+
+
 class met_tuning(ctypes.Structure):
     _fields_ = [("check_steps_per_wave", ctypes.c_int32), ("variable_chunk", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("blocks_per_cu", ctypes.c_int32), ("batch_flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class met_job(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_void_p), ("llr", ctypes.c_void_p), ("syn", ctypes.c_void_p),
+                ("B", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("bits", ctypes.c_void_p), ("iters", ctypes.c_void_p), ("converged", ctypes.c_void_p),
+                ("posterior", ctypes.c_void_p)]
 
 
 class met_check_class(ctypes.Structure):
@@ -72,7 +84,7 @@ class met_check_class(ctypes.Structure):
 def _load():
     if not os.path.exists(library_path):
         raise ImportError(
-            "libmetbp.so is not built (expected at %s); run `python -m paper_1711_01783_amd.build`" % library_path
+            "libmetbp.so is not built (expected at %s); run `python paper_1711_01783_amd/build.py`" % library_path
         )
     L = ctypes.CDLL(library_path)
     P = ctypes.c_void_p
@@ -92,6 +104,9 @@ def _load():
         "met_wbp_workspace_bytes": (ctypes.c_int, [P, i32, i32, i32, ctypes.POINTER(sz)]),
         "met_wbp_forward": (ctypes.c_int, [P, P, P, i32, i32, P, i32, P, P, P, P, sz, P]),
         "met_wbp_backward": (ctypes.c_int, [P, P, i32, i32, P, i32, P, P, sz, P]),
+        "met_batched_workspace_bytes": (ctypes.c_int, [P, i32, ctypes.POINTER(sz)]),
+        "met_decode_batched": (ctypes.c_int, [P, i32, P, sz, ctypes.POINTER(met_tuning), P]),
+        "met_batched_check": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
         "met_timing_enable": (ctypes.c_int, [i32]),
         "met_timing_collect": (ctypes.c_int, [ctypes.POINTER(met_kernel_time), i32, ctypes.POINTER(i32)]),
     }

@@ -6,7 +6,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import MET_FIXED_ITERS, check, lib, met_check_class, met_code_stats, met_kernel_time, met_profile, met_tuning
+from ._lib import (MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER, MET_FIXED_ITERS, check, lib, met_check_class,
+                   met_code_stats, met_job, met_kernel_time, met_profile, met_tuning)
 
 
 class Code:
@@ -182,6 +183,99 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
         )
     )
     return DecodeOutput(bits, iters, conv, post)
+
+
+@dataclass
+class Job:
+    """One decode job of a batched call: a code, its frames and a budget."""
+    code: Code
+    llr: "object"        # float32 [B, N] device tensor
+    syn: "object"        # uint8 [B, M] device tensor
+    max_iter: int
+    fixed_iters: bool = False
+
+
+def _job_structs(jobs, outs):
+    arr = (met_job * len(jobs))()
+    for k, (j, o) in enumerate(zip(jobs, outs)):
+        b = int(j.llr.shape[0])
+        arr[k].code = j.code.handle
+        arr[k].llr = j.llr.data_ptr()
+        arr[k].syn = j.syn.data_ptr()
+        arr[k].B = b
+        arr[k].max_iter = int(j.max_iter)
+        arr[k].flags = MET_FIXED_ITERS if j.fixed_iters else 0
+        if o is not None:
+            arr[k].bits = o.bits.data_ptr()
+            arr[k].iters = o.iterations.data_ptr()
+            arr[k].converged = o.converged.data_ptr()
+        else:  # sizing only: any non-NULL aligned value passes validation
+            arr[k].bits = arr[k].iters = arr[k].converged = 256
+        arr[k].posterior = None
+    return arr
+
+
+def batched_workspace_bytes(jobs) -> int:
+    arr = _job_structs(jobs, [None] * len(jobs))
+    n = ctypes.c_size_t()
+    check(lib.met_batched_workspace_bytes(arr, len(jobs), ctypes.byref(n)))
+    return int(n.value)
+
+
+class BatchedDecoder:
+    """Decodes a list of jobs in one persistent launch (met_decode_batched).
+
+    Keeps its workspace between calls, so repeated calls with the same jobs
+    replay the same cached HIP graph.  check_steps_per_wave / blocks_per_cu /
+    stagger / graph select launch shapes; results do not depend on them."""
+
+    def __init__(self, check_steps_per_wave: int = 0, blocks_per_cu: int = 0, stagger: bool = True,
+                 graph: bool = True):
+        self.tuning = met_tuning()
+        self.tuning.check_steps_per_wave = int(check_steps_per_wave)
+        self.tuning.blocks_per_cu = int(blocks_per_cu)
+        self.tuning.batch_flags = (0 if stagger else MET_BATCH_NO_STAGGER) | (0 if graph else MET_BATCH_NO_GRAPH)
+        self.workspace = None
+        self._ws_ptr = 0
+
+    def __call__(self, jobs, outputs=None, stream=None):
+        import torch
+
+        if not jobs:
+            raise ValueError("no jobs")
+        dev = jobs[0].llr.device
+        for j in jobs:
+            b = int(j.llr.shape[0])
+            _require(j.llr, torch.float32, (b, j.code.N), "llr")
+            _require(j.syn, torch.uint8, (b, j.code.M), "syn")
+        if outputs is None:
+            outputs = []
+            for j in jobs:
+                b = int(j.llr.shape[0])
+                outputs.append(DecodeOutput(torch.empty((b, j.code.N), dtype=torch.uint8, device=dev),
+                                            torch.empty(b, dtype=torch.int32, device=dev),
+                                            torch.empty(b, dtype=torch.uint8, device=dev), None))
+        need = batched_workspace_bytes(jobs)
+        if self.workspace is None or self.workspace.numel() - 256 < need:
+            self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+            self._ws_ptr = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        arr = _job_structs(jobs, outputs)
+        ws_len = self.workspace.numel() - (self._ws_ptr - self.workspace.data_ptr())
+        check(lib.met_decode_batched(arr, len(jobs), ctypes.c_void_p(self._ws_ptr), ws_len,
+                                     ctypes.byref(self.tuning), _stream_ptr(stream)))
+        return outputs
+
+    def barrier_expired(self) -> bool:
+        """True if the last launch's grid barrier timed out (results invalid).
+        Synchronises with the device."""
+        e = ctypes.c_int32()
+        check(lib.met_batched_check(ctypes.c_void_p(self._ws_ptr), ctypes.byref(e)))
+        return bool(e.value)
+
+
+def decode_batched(jobs, stream=None, **tuning):
+    """One-shot batched decode; returns a DecodeOutput per job."""
+    return BatchedDecoder(**tuning)(jobs, stream=stream)
 
 
 def timing_enable(on: bool = True) -> None:

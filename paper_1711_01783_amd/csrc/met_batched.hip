@@ -1,0 +1,553 @@
+// Batched decoding: several jobs (each a code, a batch of frames and an
+// iteration budget) in one persistent launch, captured in a HIP graph.
+//
+// The iterations of every job (Methods, Steps 3-5) run inside one kernel as a
+// sequence of phases separated by a grid-wide barrier.  A job's check update
+// and variable update alternate phase by phase; jobs are staggered by one
+// phase, so the same phase holds check work of some jobs (ALU-heavy) and
+// variable work of others (memory-heavy) and the two kinds share the machine.
+// Every block walks the phase's tiles of all jobs round-robin (one tile of each
+// job in turn), so each compute unit runs a mix of both kinds.  A job whose
+// budget is spent stops contributing tiles; frames that converged are retired
+// exactly as in met_decode (the same device code runs here).
+//
+// The grid is sized so that all blocks are resident at once (occupancy query),
+// which the barrier needs.  The barrier's wait is bounded: if it ever expires
+// (blocks not co-resident), an error flag is set and every block runs to its end
+// without waiting, so the launch always terminates; met_batched_check reports it.
+#include "met_gpu.h"
+
+namespace met {
+namespace {
+
+constexpr int kBatchW = 64;
+
+struct BatchJob {
+  CheckParams cp;  // per-iteration fields are set in the kernel
+  VarParams vp;
+  ClassArgs cls[kMaxClasses];
+  int32_t cls_blocks[kMaxClasses];  // tiles of each class per frame group
+  int32_t n_classes, cn_tiles, vn_blocks, G;
+  int32_t max_iter, early, offset, pad;
+  float *P, *L2;
+  uint64_t *B1, *unsat;
+  int64_t leaf_words;
+};
+
+struct BarrierState {
+  uint32_t count, gen;
+  int32_t err, pad;
+};
+
+constexpr uint32_t kSpinLimit = 1u << 22;  // polls of about 0.1 us each
+
+__device__ void grid_barrier(BarrierState *b, uint32_t nblocks) {
+  __threadfence();  // release this thread's global writes at device scope
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t gen0 = __hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
+        if (__hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (++spins == kSpinLimit) {
+          __hip_atomic_store(&b->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();  // acquire: see every block's writes of the previous phase
+}
+
+// Check tile t of job j at iteration l.
+template <int IPW, bool GEN>
+__device__ __forceinline__ void check_tile(const BatchJob &jb, int l, int64_t t) {
+  const int64_t g = t / jb.cn_tiles;
+  int64_t r = t % jb.cn_tiles;
+  int c = 0;
+  while (r >= jb.cls_blocks[c]) r -= jb.cls_blocks[c++];
+  CheckParams p = jb.cp;
+  p.it = l;
+  p.flags = jb.early && l >= 2 ? F_TEST : 0;
+  p.Pin = l == 1 ? jb.L2 : jb.P;
+  p.B1in = jb.B1 + (size_t)((l - 1) & 1) * jb.leaf_words;
+  p.B1out = jb.B1 + (size_t)(l & 1) * jb.leaf_words;
+  p.unsat = jb.unsat + (size_t)((l - 1) & 1) * jb.G;
+  p.unsat_clear = c == 0 ? jb.unsat + (size_t)(l & 1) * jb.G : nullptr;
+  const ClassArgs &a = jb.cls[c];
+  constexpr int I2 = IPW > 2 ? 2 : IPW;  // degree-11/12 checks: at most 2 steps
+  const int gi = (int)g;
+  // One compiled mode: c2v starts zero-filled, so iteration 1 needs no variant.
+  switch (a.shape) {
+    case 0: check_fixed_body<kBatchW, 3, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 1: check_fixed_body<kBatchW, 2, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 2: check_fixed_body<kBatchW, 12, 0, M_MAIN, I2, true>(p, a, r, gi); break;
+    case 3: check_fixed_body<kBatchW, 11, 0, M_MAIN, I2, true>(p, a, r, gi); break;
+    case 4: check_fixed_body<kBatchW, 6, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 5: check_fixed_body<kBatchW, 5, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    default:
+      if (GEN) check_generic_body<kBatchW, true>(p, a, r, gi);
+      break;
+  }
+}
+
+__device__ __forceinline__ void variable_tile(const BatchJob &jb, int l, int64_t t) {
+  VarParams vp = jb.vp;
+  vp.it = l;
+  vp.retire = jb.early && l >= 2;
+  vp.unsat = jb.unsat + (size_t)((l - 1) & 1) * jb.G;
+  variable_body<kBatchW, 16, true>(vp, t % jb.vn_blocks, (int)(t / jb.vn_blocks));
+}
+
+// Phase step of job j: s = phase - offset; even s: check update of iteration
+// s/2 + 1, odd s: its variable update; nothing outside [0, 2 max_iter).
+__device__ __forceinline__ int64_t job_tiles(const BatchJob &jb, int phase, int *l, int *kind) {
+  const int s = phase - jb.offset;
+  if (s < 0 || s >= 2 * jb.max_iter) return 0;
+  *l = s / 2 + 1;
+  *kind = s & 1;
+  return *kind == 0 ? (int64_t)jb.cn_tiles * jb.G : (int64_t)jb.vn_blocks * jb.G;
+}
+
+// The register budget is capped for 6 resident waves per SIMD: the launch
+// mixes memory-bound variable tiles that need many waves in flight.  Run-time
+// degree checks (GEN) are compiled only into the variant used by batches that
+// hold such classes, which keeps their register arrays out of the common one.
+template <int IPW, bool GEN>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_persistent(
+    const BatchJob *jobs, int n_jobs, int n_phases, BarrierState *bar) {
+  for (int phase = 0; phase < n_phases; ++phase) {
+    for (int64_t round = 0;; ++round) {
+      bool any = false;
+      const int64_t t = round * gridDim.x + blockIdx.x;
+      for (int j = 0; j < n_jobs; ++j) {
+        const BatchJob &jb = jobs[j];
+        int l = 0, kind = 0;
+        const int64_t n = job_tiles(jb, phase, &l, &kind);
+        if (t >= n) continue;
+        any = true;
+        if (kind == 0)
+          check_tile<IPW, GEN>(jb, l, t);
+        else
+          variable_tile(jb, l, t);
+      }
+      if (!any) break;
+    }
+    grid_barrier(bar, gridDim.x);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_floats(float *x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) x[i] = 0.0f;
+}
+
+__global__ void k_barrier_init(BarrierState *b) {
+  if (threadIdx.x == 0) {
+    b->count = 0;
+    b->gen = 0;
+    b->err = 0;
+    b->pad = 0;
+  }
+}
+
+// ----------------------------------------------------------------------------
+
+struct BatchLayout {
+  size_t off_barrier = 0, off_table = 0;
+  std::vector<size_t> off_job;
+  std::vector<Plan> plans;
+  size_t total = 0;
+};
+
+BatchLayout make_batch_layout(const met_job *jobs, int n) {
+  BatchLayout L;
+  size_t o = 0;
+  L.off_barrier = o;
+  o += 256;
+  L.off_table = o;
+  o += align256(sizeof(BatchJob) * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    Plan p = make_plan(jobs[j].code, jobs[j].B, false, false, kBatchW);
+    L.off_job.push_back(o);
+    o += p.total;
+    L.plans.push_back(p);
+  }
+  L.total = o;
+  return L;
+}
+
+int shape_ipw(int shape, int ipw) {
+  if (shape == kShapeGeneric) return 1;
+  if (kShapeMsg[shape] >= 11) return std::min(ipw, 2);
+  return ipw;
+}
+
+struct GraphEntry {
+  std::vector<uint8_t> key;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;  // small cache of instantiated graphs
+constexpr size_t kGraphCache = 8;
+
+// Graphs are captured on a library-owned stream per device (the caller's may
+// be the null stream, which cannot be captured) and launched on the caller's.
+std::mutex g_cap_mu;
+hipStream_t g_cap_stream[64] = {};
+
+int capture_stream(hipStream_t *out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MET_EHIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_cap_mu);
+  if (!g_cap_stream[dev]) HIP_TRY(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking));
+  *out = g_cap_stream[dev];
+  return MET_OK;
+}
+
+template <typename T>
+void append_bytes(std::vector<uint8_t> &k, const T &v) {
+  const uint8_t *p = reinterpret_cast<const uint8_t *>(&v);
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
+struct Batched {
+  const met_job *jobs;
+  int n;
+  char *ws;
+  hipStream_t st;
+  int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1;
+  BatchLayout L;
+  std::vector<BatchJob> table;
+  std::vector<const DeviceCode *> dev;
+  int n_phases = 0;
+  unsigned grid = 0;
+  bool gen = false;  // some class has no compiled shape
+
+  const void *kernel() const {
+    if (gen) return (const void *)k_persistent<1, true>;
+    return ipw == 4 ? (const void *)k_persistent<4, false>
+                    : ipw == 2 ? (const void *)k_persistent<2, false> : (const void *)k_persistent<1, false>;
+  }
+
+  int prepare() {
+    L = make_batch_layout(jobs, n);
+    dev.resize(n);
+    table.resize(n);
+    int max_end = 0;
+    for (int j = 0; j < n; ++j) {
+      const met_job &jb = jobs[j];
+      int rc = device_code(jb.code, &dev[j]);
+      if (rc) return rc;
+      const met_code *c = jb.code;
+      const DeviceCode *d = dev[j];
+      const Plan &pl = L.plans[j];
+      char *base = ws + L.off_job[j];
+      auto at = [&](size_t off) { return base + off; };
+      BatchJob &b = table[j];
+      std::memset(&b, 0, sizeof b);
+      b.G = pl.G;
+      b.max_iter = jb.max_iter;
+      b.early = !(jb.flags & MET_FIXED_ITERS);
+      b.offset = stagger ? (j & 1) : 0;
+      b.P = reinterpret_cast<float *>(at(pl.off_P));
+      b.L2 = reinterpret_cast<float *>(at(pl.off_L2));
+      b.B1 = reinterpret_cast<uint64_t *>(at(pl.off_B1));
+      b.unsat = reinterpret_cast<uint64_t *>(at(pl.off_unsat));
+      b.leaf_words = (int64_t)pl.G * c->EL;
+      CheckParams &cp = b.cp;
+      cp.edge_msgvn = d->edge_msgvn;
+      cp.edge_type = d->edge_type;
+      cp.leaf_type = d->leaf_type;
+      cp.chk_msg_ptr = d->chk_msg_ptr;
+      cp.chk_leaf_ptr = d->chk_leaf_ptr;
+      cp.M = c->M;
+      cp.N2 = c->N2;
+      cp.E12 = c->E12;
+      cp.EL = c->EL;
+      cp.c2v = reinterpret_cast<float *>(at(pl.off_c2v));
+      cp.c2v_in = cp.c2v;
+      cp.Lphi = reinterpret_cast<float *>(at(pl.off_Lphi));
+      cp.Lraw = pl.lraw ? reinterpret_cast<float *>(at(pl.off_Lraw)) : nullptr;
+      cp.synw = reinterpret_cast<uint64_t *>(at(pl.off_synw));
+      cp.active = reinterpret_cast<uint64_t *>(at(pl.off_active));
+      cp.G = pl.G;
+      VarParams &vp = b.vp;
+      vp.vn_ptr = d->vn_ptr;
+      vp.vn_edges = d->vn_edges;
+      vp.N2 = c->N2;
+      vp.E12 = c->E12;
+      vp.L2 = b.L2;
+      vp.c2v = cp.c2v;
+      vp.P = b.P;
+      vp.active = reinterpret_cast<uint64_t *>(at(pl.off_active));
+      vp.iters = jb.iters;
+      vp.converged = jb.converged;
+      vp.G = pl.G;
+      const std::vector<ClassArgs> cls = class_args(c);
+      b.n_classes = (int)cls.size();
+      b.vn_blocks = (int32_t)((c->N2 + kWavesPerBlock - 1) / kWavesPerBlock);
+      max_end = std::max(max_end, b.offset + 2 * jb.max_iter);
+      for (size_t k = 0; k < cls.size(); ++k) {
+        b.cls[k] = cls[k];
+        if (cls[k].shape == kShapeGeneric) gen = true;
+      }
+    }
+    if (gen) ipw = 1;
+    for (int j = 0; j < n; ++j) {
+      BatchJob &b = table[j];
+      b.cn_tiles = 0;
+      for (int k = 0; k < b.n_classes; ++k) {
+        const ClassArgs &ck = b.cls[k];
+        const int ip = shape_ipw(ck.shape, ipw);
+        const int64_t per = (int64_t)kWavesPerBlock * ip;
+        b.cls_blocks[k] = (int32_t)((ck.n_checks + per - 1) / per);
+        b.cn_tiles += b.cls_blocks[k];
+      }
+    }
+    n_phases = max_end;
+    int dev_id = 0, cus = 0, occ = 0;
+    HIP_TRY(hipGetDevice(&dev_id));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+    const void *kfn = kernel();
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kBlock, 0));
+    if (occ < 1) return fail(MET_EHIP, "persistent kernel cannot be resident");
+    const int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ;
+    grid = (unsigned)(per_cu * cus);
+    return MET_OK;
+  }
+
+  // Everything after the job table copy: set-up, persistent iterations, outputs.
+  void enqueue() {
+    for (int j = 0; j < n; ++j) {
+      const met_job &jb = jobs[j];
+      const met_code *c = jb.code;
+      const DeviceCode *d = dev[j];
+      const Plan &pl = L.plans[j];
+      char *base = ws + L.off_job[j];
+      InitParams ip{};
+      ip.llr = jb.llr;
+      ip.syn = jb.syn;
+      ip.msg_vn_user = d->msg_vn_user;
+      ip.leaf_vn = d->leaf_vn;
+      ip.N = c->N;
+      ip.M = c->M;
+      ip.N2 = c->N2;
+      ip.EL = c->EL;
+      ip.B = jb.B;
+      ip.G = pl.G;
+      ip.Lt = reinterpret_cast<float *>(base + pl.off_c2v);
+      ip.L2 = reinterpret_cast<float *>(base + pl.off_L2);
+      ip.Lphi = reinterpret_cast<float *>(base + pl.off_Lphi);
+      ip.Lraw = pl.lraw ? reinterpret_cast<float *>(base + pl.off_Lraw) : nullptr;
+      ip.synw = reinterpret_cast<uint64_t *>(base + pl.off_synw);
+      ip.active = reinterpret_cast<uint64_t *>(base + pl.off_active);
+      ip.unsat = reinterpret_cast<uint64_t *>(base + pl.off_unsat);
+      ip.iters = jb.iters;
+      ip.converged = jb.converged;
+      const int G = pl.G;
+      hipLaunchKernelGGL(k_transpose<kBatchW>, dim3((unsigned)((c->N + 63) / 64), G), dim3(kBlock), 0, st, ip);
+      const int64_t ni = (c->N2 + c->EL) * kBatchW;
+      if (ni > 0)
+        hipLaunchKernelGGL(k_init_items<kBatchW>, dim3((unsigned)((ni + kBlock - 1) / kBlock), G), dim3(kBlock), 0,
+                           st, ip);
+      hipLaunchKernelGGL(k_pack_syndrome<kBatchW>,
+                         dim3((unsigned)std::max<int64_t>(1, (c->M + kBlock - 1) / kBlock), G), dim3(kBlock), 0, st,
+                         ip);
+    }
+    for (int j = 0; j < n; ++j) {
+      const Plan &pl = L.plans[j];
+      const int64_t nc = (int64_t)pl.G * jobs[j].code->E12 * kBatchW;
+      if (nc > 0)
+        hipLaunchKernelGGL(k_zero_floats, dim3((unsigned)std::min<int64_t>(8192, (nc + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, reinterpret_cast<float *>(ws + L.off_job[j] + pl.off_c2v), nc);
+    }
+    BarrierState *bar = reinterpret_cast<BarrierState *>(ws + L.off_barrier);
+    const BatchJob *tab = reinterpret_cast<const BatchJob *>(ws + L.off_table);
+    hipLaunchKernelGGL(k_barrier_init, dim3(1), dim3(64), 0, st, bar);
+    {
+      ScopedTimer t(st, "k_persistent");
+      void *args[] = {(void *)&tab, (void *)&n, (void *)&n_phases, (void *)&bar};
+      (void)hipLaunchKernel(kernel(), dim3(grid), dim3(kBlock), args, 0, st);
+    }
+    for (int j = 0; j < n; ++j) {
+      const met_job &jb = jobs[j];
+      const met_code *c = jb.code;
+      const DeviceCode *d = dev[j];
+      const Plan &pl = L.plans[j];
+      char *base = ws + L.off_job[j];
+      const int G = pl.G;
+      const size_t leaf_words = (size_t)G * c->EL, leaf_floats = leaf_words * kBatchW;
+      uint64_t *B1 = reinterpret_cast<uint64_t *>(base + pl.off_B1);
+      uint64_t *unsat = reinterpret_cast<uint64_t *>(base + pl.off_unsat);
+      float *P1 = nullptr;
+      TestParams tp{};
+      tp.edge_msgvn = d->edge_msgvn;
+      tp.chk_msg_ptr = d->chk_msg_ptr;
+      tp.chk_leaf_ptr = d->chk_leaf_ptr;
+      tp.M = c->M;
+      tp.N2 = c->N2;
+      tp.E12 = c->E12;
+      tp.EL = c->EL;
+      tp.P = reinterpret_cast<float *>(base + pl.off_P);
+      tp.synw = reinterpret_cast<uint64_t *>(base + pl.off_synw);
+      tp.B1 = B1 + (size_t)(jb.max_iter & 1) * leaf_words;
+      tp.active = reinterpret_cast<uint64_t *>(base + pl.off_active);
+      tp.unsat = unsat + (size_t)(jb.max_iter & 1) * G;
+      const int64_t per = kWavesPerBlock;
+      hipLaunchKernelGGL(k_test<kBatchW>, dim3((unsigned)((c->M + per - 1) / per), G), dim3(kBlock), 0, st, tp);
+      FinalParams fp{};
+      fp.vn_slot = d->vn_slot;
+      fp.N = c->N;
+      fp.N2 = c->N2;
+      fp.EL = c->EL;
+      fp.B = jb.B;
+      fp.max_iter = jb.max_iter;
+      fp.P = tp.P;
+      fp.P1a = P1;
+      fp.P1b = P1 ? P1 + leaf_floats : nullptr;
+      fp.B1a = B1;
+      fp.B1b = B1 + leaf_words;
+      fp.active = tp.active;
+      fp.unsat_last = tp.unsat;
+      fp.iters = jb.iters;
+      fp.converged = jb.converged;
+      fp.bits = jb.bits;
+      fp.posterior = jb.posterior;
+      fp.G = G;
+      hipLaunchKernelGGL(k_final_status<kBatchW>, dim3((jb.B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fp);
+      hipLaunchKernelGGL(k_finalize<kBatchW>, dim3((unsigned)((c->N + 63) / 64), G), dim3(kBlock), 0, st, fp);
+    }
+  }
+
+  std::vector<uint8_t> key() const {
+    std::vector<uint8_t> k;
+    append_bytes(k, ws);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    append_bytes(k, dev);
+    append_bytes(k, ipw);
+    append_bytes(k, gen);
+    append_bytes(k, grid);
+    append_bytes(k, n_phases);
+    for (int j = 0; j < n; ++j) append_bytes(k, jobs[j]);
+    return k;
+  }
+
+  int run() {
+    int rc = prepare();
+    if (rc) return rc;
+    // the job table is stream-ordered before the graph (or the plain launches)
+    HIP_TRY(hipMemcpyAsync(ws + L.off_table, table.data(), sizeof(BatchJob) * table.size(), hipMemcpyHostToDevice,
+                           st));
+    if (!use_graph || g_timing.on) {
+      enqueue();
+      HIP_TRY(hipGetLastError());
+      return MET_OK;
+    }
+    const std::vector<uint8_t> k = key();
+    hipGraphExec_t exec = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(g_graph_mu);
+      for (const GraphEntry &e : g_graphs)
+        if (e.key == k) exec = e.exec;
+    }
+    if (!exec) {
+      hipStream_t cap = nullptr;
+      rc = capture_stream(&cap);
+      if (rc) return rc;
+      const hipStream_t user = st;
+      st = cap;
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      enqueue();
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(cap, &graph);
+      st = user;
+      if (le != hipSuccess) return fail(MET_EHIP, "launch during capture: %s", hipGetErrorString(le));
+      if (ce != hipSuccess) return fail(MET_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+      const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) return fail(MET_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+      std::lock_guard<std::mutex> lock(g_graph_mu);
+      if (g_graphs.size() == kGraphCache) {
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+      }
+      g_graphs.push_back({k, exec});
+    }
+    HIP_TRY(hipGraphLaunch(exec, st));
+    return MET_OK;
+  }
+};
+
+}  // namespace
+}  // namespace met
+
+using met::fail;
+
+static int validate_jobs(const met_job *jobs, int32_t n) {
+  if (!jobs || n < 1 || n > 64) return fail(MET_EINVAL, "n_jobs = %d outside 1..64", n);
+  for (int j = 0; j < n; ++j) {
+    const met_job &b = jobs[j];
+    if (!b.code) return fail(MET_EINVAL, "job %d: NULL code", j);
+    if (b.B < 1 || b.B > 65535) return fail(MET_EINVAL, "job %d: B = %d outside 1..65535", j, b.B);
+    if (b.max_iter < 1 || b.max_iter > 1000000) return fail(MET_EINVAL, "job %d: bad max_iter", j);
+    if (b.flags & ~(uint32_t)MET_FIXED_ITERS) return fail(MET_EINVAL, "job %d: unknown flags", j);
+    if (!b.llr || !b.syn || !b.bits || !b.iters || !b.converged) return fail(MET_EINVAL, "job %d: NULL buffer", j);
+    if (b.posterior) return fail(MET_EINVAL, "job %d: posterior output is not available in batched mode", j);
+    if (((uintptr_t)b.llr & 3) || ((uintptr_t)b.posterior & 3) || ((uintptr_t)b.iters & 3))
+      return fail(MET_EINVAL, "job %d: misaligned buffer", j);
+  }
+  return MET_OK;
+}
+
+extern "C" int met_batched_workspace_bytes(const met_job *jobs, int32_t n_jobs, size_t *bytes) {
+  met::clear_error();
+  int rc = validate_jobs(jobs, n_jobs);
+  if (rc) return rc;
+  if (!bytes) return fail(MET_EINVAL, "NULL bytes");
+  *bytes = met::make_batch_layout(jobs, n_jobs).total;
+  return MET_OK;
+}
+
+extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
+                                  const met_tuning *tuning, void *stream) {
+  met::clear_error();
+  int rc = validate_jobs(jobs, n_jobs);
+  if (rc) return rc;
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(MET_EINVAL, "workspace NULL or not 256-byte aligned");
+  const size_t need = met::make_batch_layout(jobs, n_jobs).total;
+  if (ws_bytes < need) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  met::Batched b{jobs, n_jobs, static_cast<char *>(workspace), (hipStream_t)stream};
+  if (tuning) {
+    const int s = tuning->check_steps_per_wave;
+    if (s != 0 && s != 1 && s != 2 && s != 4) return fail(MET_EINVAL, "check_steps_per_wave must be 0, 1, 2 or 4");
+    if (s) b.ipw = s;
+    if (tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > 64) return fail(MET_EINVAL, "bad blocks_per_cu");
+    b.blocks_per_cu = tuning->blocks_per_cu;
+    if (tuning->batch_flags & ~3) return fail(MET_EINVAL, "unknown batch_flags");
+    b.stagger = !(tuning->batch_flags & MET_BATCH_NO_STAGGER);
+    b.use_graph = !(tuning->batch_flags & MET_BATCH_NO_GRAPH);
+    for (int r = 0; r < 4; ++r)
+      if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
+  }
+  return b.run();
+}
+
+extern "C" int met_batched_check(const void *workspace, int32_t *barrier_expired) {
+  met::clear_error();
+  if (!workspace || !barrier_expired) return fail(MET_EINVAL, "NULL argument");
+  met::BarrierState s{};
+  const hipError_t e = hipMemcpy(&s, workspace, sizeof s, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(MET_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+  *barrier_expired = s.err;
+  return MET_OK;
+}

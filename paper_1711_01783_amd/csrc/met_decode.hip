@@ -345,7 +345,7 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
     const int u = tuning->variable_chunk;
     if (u != 0 && u != 8 && u != 16 && u != 32) return fail(MET_EINVAL, "variable_chunk must be 0, 8, 16 or 32");
     if (u) chunk = u;
-    for (int r = 0; r < 6; ++r)
+    for (int r = 0; r < 4; ++r)
       if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
   }
   const int W = met::choose_interleave(B);

@@ -180,21 +180,28 @@ __device__ __forceinline__ void store_leaf_word(uint64_t *dst, uint64_t ball, in
   *dst = (act == wmask<W>()) ? chunk : ((*dst & ~act) | (chunk & act));
 }
 
-__device__ __forceinline__ void clear_next_unsat(const CheckParams &p) {
-  if (p.unsat_clear && blockIdx.x == 0 && blockIdx.y == 0)
+__device__ __forceinline__ void clear_next_unsat(const CheckParams &p, int64_t bx, int g) {
+  if (p.unsat_clear && bx == 0 && g == 0)
     for (int gg = threadIdx.x; gg < p.G; gg += kBlock) p.unsat_clear[gg] = 0ull;
+}
+
+// Loads of words that an earlier phase of the same persistent launch may have
+// written: vector loads at device scope (never the scalar cache).
+template <bool PERSIST>
+__device__ __forceinline__ uint64_t ld_word(const uint64_t *p, int64_t i) {
+  if (PERSIST) return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return ldro(p, i);
 }
 
 // Check update of one class of checks with a compile-time shape (NM message
 // edges, NL leaf edges per check).  Each wave takes IPW consecutive steps of
 // 64/W checks; all loads of its checks are issued before any arithmetic.
-template <int W, int NM, int NL, int MODE, int IPW>
-__global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, const ClassArgs c) {
+template <int W, int NM, int NL, int MODE, int IPW, bool PERSIST>
+__device__ __forceinline__ void check_fixed_body(const CheckParams &p, const ClassArgs &c, int64_t bx, int g) {
   constexpr int D = NM + NL;
   constexpr int IPWAVE = 64 / W;
-  clear_next_unsat(p);
-  const int g = blockIdx.y;
-  const uint64_t act = p.active[g];
+  clear_next_unsat(p, bx, g);
+  const uint64_t act = PERSIST ? ld_word<true>(p.active, g) : p.active[g];
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int w = lane % W, q = lane / W;
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, con
   const bool test = MODE != M_FIRST && (p.flags & F_TEST);
   const bool post = MODE == M_SPECIAL && (p.flags & F_POST);
   const bool weighted = MODE == M_SPECIAL && (p.flags & F_WEIGHTED);
-  const int64_t base = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * IPW * IPWAVE;
+  const int64_t base = (bx * kWavesPerBlock + wv) * IPW * IPWAVE;
   if (W == 64 && base >= c.n_checks) return;
 
   int64_t item[IPW];
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, con
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       lf[k][l] = p.Lphi[((int64_t)g * p.EL + l0 + l) * W + w];
-      b1[k][l] = test ? ldro(p.B1in, (int64_t)g * p.EL + l0 + l) : 0ull;
+      b1[k][l] = test ? ld_word<PERSIST>(p.B1in, (int64_t)g * p.EL + l0 + l) : 0ull;
     }
   }
   uint32_t bad = 0;
@@ -301,19 +308,23 @@ __global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, con
   }
 }
 
+template <int W, int NM, int NL, int MODE, int IPW>
+__global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, const ClassArgs c) {
+  check_fixed_body<W, NM, NL, MODE, IPW, false>(p, c, blockIdx.x, blockIdx.y);
+}
+
 // Check update with run-time degrees (total degree <= MET_MAX_CHECK_DEGREE),
 // for classes without a compiled shape.  One check per lane group.
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, const ClassArgs c) {
+template <int W, bool PERSIST>
+__device__ __forceinline__ void check_generic_body(const CheckParams &p, const ClassArgs &c, int64_t bx, int g) {
   constexpr int D = MET_MAX_CHECK_DEGREE;
-  clear_next_unsat(p);
-  const int g = blockIdx.y;
-  const uint64_t act = p.active[g];
+  clear_next_unsat(p, bx, g);
+  const uint64_t act = PERSIST ? ld_word<true>(p.active, g) : p.active[g];
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int w = lane % W, q = lane / W;
   const bool lane_act = (act >> w) & 1ull;
-  const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * (64 / W) + q;
+  const int64_t i = (bx * kWavesPerBlock + wv) * (64 / W) + q;
   if (W == 64 && i >= c.n_checks) return;
   const bool valid = i < c.n_checks;
   const int64_t j = c.first_check + (valid ? i : 0);
@@ -341,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, c
       const float f = p.Lphi[((int64_t)g * p.EL + le) * W + w];
       A[k] = fabsf(f);
       neg |= sign_bit(f) << k;
-      if (test) parity ^= (uint32_t)(p.B1in[(int64_t)g * p.EL + le] >> w) & 1u;
+      if (test) parity ^= (uint32_t)(ld_word<PERSIST>(p.B1in, (int64_t)g * p.EL + le) >> w) & 1u;
     }
   }
   const uint32_t bad = test ? (parity & (uint32_t)(valid && lane_act)) : 0u;
@@ -406,6 +417,11 @@ __global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, c
   }
 }
 
+template <int W>
+__global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, const ClassArgs c) {
+  check_generic_body<W, false>(p, c, blockIdx.x, blockIdx.y);
+}
+
 // Syndrome test only (after the last iteration): parity of the hard decisions
 // of P^l (message VNs) and of the stored leaf decisions against s.
 struct TestParams {
@@ -451,16 +467,16 @@ struct VarParams {
 
 // Variable update: P_v = L_v + sum of c2v over v's message edges (gathered U
 // at a time, summed in list order).
-template <int W, int U>
-__global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
-  const int g = blockIdx.y;
-  uint64_t act = p.active[g];
+template <int W, int U, bool PERSIST>
+__device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, int g) {
+  uint64_t act = PERSIST ? ld_word<true>(p.active, g) : p.active[g];
   if (p.retire) {
     // Frames whose test of iteration it-1 passed stop here; their P stays at
     // iteration it-1.  Block (0,0) records the outcome for every group.
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (bx == 0 && g == 0) {
       for (int gg = threadIdx.x; gg < p.G; gg += kBlock) {
-        const uint64_t a = p.active[gg], u = p.unsat[gg];
+        const uint64_t a = PERSIST ? ld_word<true>(p.active, gg) : p.active[gg];
+        const uint64_t u = PERSIST ? ld_word<true>(p.unsat, gg) : p.unsat[gg];
         const uint64_t done = a & ~u;
         if (done) {
           for (int w = 0; w < W; ++w)
@@ -473,12 +489,12 @@ __global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
         }
       }
     }
-    act &= p.unsat[g];
+    act &= PERSIST ? ld_word<true>(p.unsat, g) : p.unsat[g];
   }
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id(), w = lane % W, q = lane / W;
   const bool lane_act = (act >> w) & 1ull;
-  const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * (64 / W) + q;
+  const int64_t i = (bx * kWavesPerBlock + wv) * (64 / W) + q;
   if (i >= p.N2) return;
   const int32_t e0 = ldro(p.vn_ptr, i), e1 = ldro(p.vn_ptr, i + 1);
   float P = p.L2[((int64_t)g * p.N2 + i) * W + w];
@@ -501,6 +517,11 @@ __global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
     }
   for (; e < e1; ++e) P += c2v[(int64_t)ldro(p.vn_edges, e) * W];
   if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
+}
+
+template <int W, int U>
+__global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
+  variable_body<W, U, false>(p, blockIdx.x, blockIdx.y);
 }
 
 // ----------------------------------------------------------------------------

@@ -147,3 +147,45 @@ def test_free_is_idempotent():
     c.close()
     c.close()
     _lib.lib.met_code_free(None)
+
+
+def test_batched_argument_validation_without_gpu():
+    c1 = met.Code.build(PROFILES["r0.1"], 4096, 1)
+    c2 = met.Code.build(PROFILES["r0.02"], 3000, 2)
+    L = _lib.lib
+    P = ctypes.c_void_p
+    jobs = (_lib.met_job * 2)()
+    for k, (c, b) in enumerate(((c1, 64), (c2, 100))):
+        jobs[k].code = c.handle
+        jobs[k].llr = jobs[k].syn = jobs[k].bits = jobs[k].iters = jobs[k].converged = 256
+        jobs[k].B = b
+        jobs[k].max_iter = 20
+    n = ctypes.c_size_t()
+    assert L.met_batched_workspace_bytes(jobs, 2, ctypes.byref(n)) == 0
+    both = n.value
+    assert L.met_batched_workspace_bytes(jobs, 1, ctypes.byref(n)) == 0 and 0 < n.value < both
+    # each job's part is at least what met_decode needs for the same frames
+    assert both >= met.workspace_bytes(c1, 64) + met.workspace_bytes(c2, 100)
+    assert L.met_batched_workspace_bytes(jobs, 0, ctypes.byref(n)) == -1
+    jobs[1].posterior = 256
+    assert L.met_batched_workspace_bytes(jobs, 2, ctypes.byref(n)) == -1
+    assert "posterior" in L.met_last_error().decode()
+    jobs[1].posterior = None
+    jobs[1].flags = 8
+    assert L.met_batched_workspace_bytes(jobs, 2, ctypes.byref(n)) == -1
+    jobs[1].flags = 0
+    jobs[0].B = 0
+    assert L.met_batched_workspace_bytes(jobs, 2, ctypes.byref(n)) == -1
+    jobs[0].B = 64
+    jobs[0].llr = 258
+    assert L.met_decode_batched(jobs, 2, P(256), both, None, None) == -1
+    jobs[0].llr = 256
+    assert L.met_decode_batched(jobs, 2, P(264), both, None, None) == -1   # workspace misaligned
+    assert L.met_decode_batched(jobs, 2, P(256), both - 1, None, None) == -1
+    t = _lib.met_tuning()
+    t.check_steps_per_wave = 3
+    assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
+    t.check_steps_per_wave = 0
+    t.batch_flags = 4
+    assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
+    assert L.met_batched_check(None, None) == -1
