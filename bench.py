@@ -1,20 +1,30 @@
 #!/usr/bin/env python3
 """Decoded Mbit/s of syndrome BP on MET-LDPC codes on one MI355X.
 
-A step is one decode call over one batch: flooding sum-product BP of the
-paper's Methods (Steps 2-5) on B frames of a rate-0.1 MET code with N = 10^6,
-every part of the hot path (input layout, check and variable kernels, syndrome
-tests, output) on the GPU.  Inputs are resident in HBM before the timed region.
+Default workload (``--workload mix``): three MET codes with N = 10^6 -- rates
+0.1, 0.05 and 0.02 -- with 64 frames each at SNR 0.157 / 0.0757 / 0.0296 and
+iteration budgets 100 / 150 / 200 (per-frame early exit).  A step decodes all
+three batches: flooding sum-product BP of the paper's Methods (Steps 2-5) with
+every part of the hot path (input layout, check and variable updates, syndrome
+tests, outputs) on the GPU.  ``value`` is the batched form (all jobs in one
+persistent launch captured in a HIP graph); the plain form (one decode call
+per job, run one after the other) is timed on the same inputs and reported
+beside it, with each job's FER for both (they decode identically).
 
-    python bench.py [--steps K] [--warmup W] [--profile r0.1|r0.05|r0.02] ...
+``--workload single`` times the plain decoder on one code (default rate 0.1,
+N = 10^6, 64 frames, SNR 0.157, 100 iterations).
+
+    python bench.py [--steps K] [--warmup W] [--workload mix|single] ...
 
 Prints one JSON line.  Speed counts N decoded bits per frame, as the paper's
-Table 1 does (speed = N / (iterations x per-codeword latency)).
+Table 1 does (speed = N / (iterations x per-codeword latency)).  Inputs are
+resident in HBM before the timed region.
 
-The roofline object reports the check kernel, which moves most of the bytes:
-algorithmic bytes per launch (unique bytes a launch must read or write, see
-``check_bytes_per_frame``) divided by the kernel's average duration, measured
-with HIP events bracketing each launch on the decode stream.
+The roofline object reports the kernel that moves most of the bytes (the
+persistent kernel for the mix, the largest check class for a single code):
+algorithmic bytes per launch (unique bytes it must read or write, see
+``class_bytes_per_frame`` / ``variable_bytes_per_frame``) over its average
+duration, measured with HIP events bracketing each launch on its stream.
 """
 from __future__ import annotations
 
@@ -36,7 +46,9 @@ METRIC = "decoded Mbit/s at N=1e6, R=0.1/0.05/0.02 (batched vs plain, equal FER)
 HBM_PEAK_GBS = 8000.0
 CODE_SEED = {"r0.1": 101, "r0.05": 102, "r0.02": 103}
 FRAME_SEED = 5000
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_check_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+MIX = ("r0.1", "r0.05", "r0.02")
+KERNEL_SOURCES = ("met_gpu.h", "met_decode.hip", "met_batched.hip")
 
 
 def class_bytes_per_frame(cls: dict, W: int, first: bool = False, test: bool = True) -> float:
@@ -86,44 +98,56 @@ def wilson(k: int, n: int, z: float = 1.96):
 _CPU = {}
 
 
-def _cpu_worker(f):
+def _cpu_worker(task):
     os.environ["OMP_NUM_THREADS"] = "1"
     from oracle import bp
     from oracle import code as oc
 
-    code = _CPU["code"]
-    bits, llr = make_frames(code.n, 1, _CPU["snr"], FRAME_SEED, first_frame=f)
+    prof, f = task
+    code = _CPU["codes"][prof]
+    bits, llr = make_frames(code.n, 1, BJ_SNR[prof] if _CPU["snr"] is None else _CPU["snr"], FRAME_SEED,
+                            first_frame=f)
     syn = oc.syndrome(code, bits)
     t0 = time.perf_counter()
     bp.decode(code, llr, syn, _CPU["iters"], early_exit=False)
-    return time.perf_counter() - t0
+    return prof, time.perf_counter() - t0
 
 
-def cpu_baseline(prof: str, n: int, snr: float, budget: int, sample_iters: int, max_workers: int) -> dict:
+def cpu_baseline(jobs, n: int, snr, sample_iters: int, max_workers: int) -> dict:
+    """jobs: [(profile, frames, budget)].  Each host core decodes one frame of
+    one job's code for sample_iters iterations (fixed mode); per-iteration times
+    are extrapolated to the whole workload (every frame its full budget, as at
+    these SNRs) spread over the cores."""
     import multiprocessing as mp
 
     from oracle import code as oc
 
     cores = len(os.sched_getaffinity(0))
     workers = max(1, min(cores, max_workers))
-    _CPU["code"] = oc.build(PROFILES[prof], n, CODE_SEED[prof])
+    _CPU["codes"] = {p: oc.build(PROFILES[p], n, CODE_SEED[p]) for p, _, _ in jobs}
     _CPU["snr"] = snr
     _CPU["iters"] = sample_iters
+    tasks = [(jobs[k % len(jobs)][0], k) for k in range(workers)]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(workers) as pool:
-        durs = pool.map(_cpu_worker, range(workers))
+        durs = pool.map(_cpu_worker, tasks)
     wall = time.perf_counter() - t0
-    per_frame_full = max(durs) * budget / sample_iters
-    mbit = workers * n / per_frame_full / 1e6
+    per_iter = {}
+    for prof, d in durs:
+        per_iter.setdefault(prof, []).append(d / sample_iters)
+    cpu_seconds = sum(b * budget * max(per_iter[p]) for p, b, budget in jobs)
+    bits = sum(b for _, b, _ in jobs) * n
+    mbit = bits / (cpu_seconds / workers) / 1e6
     return {
         "value": round(mbit, 4),
         "unit": "Mbit/s",
         "cores": workers,
         "kind": "oracle",
-        "sample": "%d frames (one per core) of the same workload, %d of %d iterations each in fixed mode, "
-        "slowest frame's decode time extrapolated linearly to the full budget (wall %.1f s)"
-        % (workers, sample_iters, budget, wall),
+        "sample": "%d frames (one per core: %s), %d iterations each in fixed mode; the slowest frame's time per "
+        "iteration of each code, times frames x budget of the workload, spread over %d cores (wall %.1f s)"
+        % (workers, ", ".join("%d of %s" % (sum(1 for t in tasks if t[0] == p), p) for p, _, _ in jobs),
+           sample_iters, workers, wall),
     }
 
 
@@ -131,22 +155,267 @@ def cpu_baseline(prof: str, n: int, snr: float, budget: int, sample_iters: int, 
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1711_01783_amd", "csrc", "met_decode.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1711_01783_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key: str):
-    """HBM bytes per check-kernel launch from the committed counter summary,
-    or None when it is missing or the kernel source changed since."""
+def measured_traffic(kernel: str, workload_key: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when it is missing or the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash() or t.get("workload") != workload_key:
+    e = t.get(kernel + " | " + workload_key)
+    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return e.get("bytes_per_launch")
+
+
+def active_frames(iters, conv, max_iter: int, early: bool):
+    """Frames taking part in check update l and in variable update l, l = 1..max_iter:
+    a frame that converged at iteration r runs check updates 1..r+1 (update r+1
+    carries its test) and variable updates 1..r."""
+    import numpy as np
+
+    if not early:
+        full = np.full(max_iter, len(iters))
+        return full, full
+    last_c = np.where(conv == 1, np.minimum(iters + 1, max_iter), max_iter)
+    last_v = np.where(conv == 1, iters, max_iter)
+    ls = np.arange(1, max_iter + 1)
+    return (last_c[None, :] >= ls[:, None]).sum(1), (last_v[None, :] >= ls[:, None]).sum(1)
+
+
+def job_bytes(code, iters, conv, max_iter: int, early: bool, W: int = 64):
+    """Algorithmic bytes of one decode of a job: (check updates by class name,
+    variable updates)."""
+    classes = [c for c in code.classes() if c["n_msg"] >= 0]
+    st = code.info()
+    fc, fv = active_frames(iters, conv, max_iter, early)
+    per_class = {}
+    for c in classes:
+        name = "k_check<%d,%d>" % (c["n_msg"], c["n_leaf"])
+        b = 0.0
+        for l in range(1, max_iter + 1):
+            b += fc[l - 1] * class_bytes_per_frame(c, W, first=(l == 1), test=(early and l >= 2))
+        per_class[name] = per_class.get(name, 0.0) + b
+    var = float(fv.sum()) * variable_bytes_per_frame(st, W)
+    return per_class, var
+
+
+def roofline(kernel: str, bytes_total: float, launches: int, total_ms: float, traffic) -> dict:
+    avg_ms = total_ms / max(1, launches)
+    per_launch = bytes_total / max(1, launches)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return {
+        "kernel": kernel,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": round(per_launch),
+        "avg_launch_us": round(avg_ms * 1e3, 2),
+    }
+
+
+def timed(fn, steps: int, warmup: int):
+    """Runs fn warmup times, then `steps` times between two events with the
+    decoder's per-launch timing on; returns (elapsed ms, kernel times, last out)."""
+    import torch
+
+    import paper_1711_01783_amd as met
+
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    met.timing_enable(True)
+    met.timing_collect()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        out = fn()
+    stop.record()
+    torch.cuda.synchronize()
+    ktimes = met.timing_collect()
+    met.timing_enable(False)
+    return start.elapsed_time(stop), ktimes, out
+
+
+def timed_plain(fn, steps: int) -> float:
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop)
+
+
+def fer_summary(out, bits):
+    import numpy as np
+
+    dec = out.bits.cpu().numpy()
+    conv = out.converged.cpu().numpy()
+    iters = out.iterations.cpu().numpy()
+    err = np.any(dec != bits, axis=1)
+    k, b = int(err.sum()), len(err)
+    lo, hi = wilson(k, b)
+    return {"fer": round(k / b, 4), "fer_ci95": [round(lo, 4), round(hi, 4)], "converged": int(conv.sum()),
+            "undetected_errors": int((err & (conv == 1)).sum()), "mean_iterations": round(float(iters.mean()), 2)}
+
+
+def run_mix(args, cpu) -> dict:
+    import numpy as np
+    import torch
+
+    import paper_1711_01783_amd as met
+
+    dev = torch.device("cuda:0")
+    n, B = args.n, args.frames
+    jobs, truth = [], []
+    for prof in MIX:
+        code = met.Code.build(PROFILES[prof], n, CODE_SEED[prof])
+        snr = args.snr if args.snr is not None else BJ_SNR[prof]
+        bits, llr = make_frames(n, B, snr, FRAME_SEED)
+        syn = met.syndrome(code, torch.from_numpy(bits).to(dev))
+        budget = args.max_iter if args.max_iter is not None else ITER_BUDGET[prof]
+        jobs.append(met.Job(code, torch.from_numpy(llr).to(dev), syn, budget, args.fixed_iters))
+        truth.append(bits)
+    wss = [torch.empty(met.workspace_bytes(j.code, B, j.fixed_iters) + 256, dtype=torch.uint8, device=dev)
+           for j in jobs]
+    torch.cuda.synchronize()
+    early = not args.fixed_iters
+
+    def plain():
+        return [met.decode(j.code, j.llr, j.syn, j.max_iter, fixed_iters=j.fixed_iters, workspace=w,
+                           check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
+                for j, w in zip(jobs, wss)]
+
+    p_ms, p_kt, p_out = timed(plain, args.steps, args.warmup)
+    del wss
+    dec = met.BatchedDecoder(check_steps_per_wave=args.check_steps, blocks_per_cu=args.blocks_per_cu)
+    b_ms, b_kt, b_out = timed(lambda: dec(jobs), args.steps, args.warmup)
+    expired = dec.barrier_expired()
+    # per-launch timing runs the launch sequence outside a graph; the same steps
+    # replayed from the captured graph, without events:
+    g_ms = timed_plain(lambda: dec(jobs), args.steps)
+    expired = expired or dec.barrier_expired()
+    same = all(np.array_equal(a.bits.cpu().numpy(), b.bits.cpu().numpy())
+               and np.array_equal(a.iterations.cpu().numpy(), b.iterations.cpu().numpy())
+               for a, b in zip(p_out, b_out))
+
+    total_bits = B * n * len(jobs) * args.steps
+    b_val = total_bits / (b_ms * 1e-3) / 1e6
+    p_val = total_bits / (p_ms * 1e-3) / 1e6
+    wl = "batched mix: rates 0.1/0.05/0.02 N=%d B=%d each, budgets %s, %s" % (
+        n, B, "/".join(str(j.max_iter) for j in jobs), "fixed" if args.fixed_iters else "early-exit")
+
+    # algorithmic bytes of one step, per kernel, from each job's outcome
+    check_bytes, var_bytes = {}, 0.0
+    per_job = []
+    for prof, j, o, bits in zip(MIX, jobs, b_out, truth):
+        cls, var = job_bytes(j.code, o.iterations.cpu().numpy(), o.converged.cpu().numpy(), j.max_iter, early)
+        for k, v in cls.items():
+            check_bytes[k] = check_bytes.get(k, 0.0) + v
+        var_bytes += var
+        d = {"profile": prof, "snr": float(args.snr if args.snr is not None else BJ_SNR[prof]),
+             "max_iter": j.max_iter}
+        d.update(fer_summary(o, bits))
+        d["plain_fer"] = fer_summary(p_out[len(per_job)], bits)["fer"]
+        per_job.append(d)
+    step_bytes = sum(check_bytes.values()) + var_bytes
+    kl, kms = b_kt.get("k_persistent", (0, 0.0))
+    roof = roofline("k_persistent", step_bytes * args.steps, kl, kms, measured_traffic("k_persistent", wl))
+    pl, pms = p_kt.get("k_check<3,1>", (0, 0.0))
+    plain_roof = roofline("k_check<3,1>", check_bytes.get("k_check<3,1>", 0.0) * args.steps, pl, pms,
+                          measured_traffic("k_check<3,1>", wl))
+    return {
+        "value": round(b_val, 3),
+        "ms_per_step": round(b_ms / args.steps, 3),
+        "config": {
+            "workload": "batched persistent launch of three jobs: MET codes of rate 0.1, 0.05 and 0.02 at N=%d, "
+            "%d frames each, SNR %s, max %s iterations, %s; value = batched form"
+            % (n, B, "/".join("%g" % d["snr"] for d in per_job), "/".join(str(j.max_iter) for j in jobs),
+               "fixed iterations" if args.fixed_iters else "per-frame early exit"),
+            "N": n, "frames_per_job": B, "profiles": list(MIX), "code_seeds": [CODE_SEED[p] for p in MIX],
+            "frame_seed": FRAME_SEED, "mode": "batched", "interleave": 64,
+        },
+        "roofline": roof,
+        "plain": {"value": round(p_val, 3), "ms_per_step": round(p_ms / args.steps, 3),
+                  "roofline": plain_roof,
+                  "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)}
+                                 for k, v in p_kt.items()}},
+        "batched_over_plain": round(b_val / p_val, 4),
+        "graph_replay": {"value": round(total_bits / (g_ms * 1e-3) / 1e6, 3),
+                         "ms_per_step": round(g_ms / args.steps, 3)},
+        "identical_outputs": bool(same),
+        "barrier_expired": bool(expired),
+        "jobs": per_job,
+        "bytes_per_step": {"check": check_bytes, "variable": var_bytes},
+        "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)} for k, v in b_kt.items()},
+    }
+
+
+def run_single(args, cpu) -> dict:
+    import numpy as np
+    import torch
+
+    import paper_1711_01783_amd as met
+
+    prof = args.profile
+    snr = args.snr if args.snr is not None else BJ_SNR[prof]
+    max_iter = args.max_iter if args.max_iter is not None else ITER_BUDGET[prof]
+    n, B = args.n, args.frames
+    dev = torch.device("cuda:0")
+    code = met.Code.build(PROFILES[prof], n, CODE_SEED[prof])
+    bits, llr = make_frames(n, B, snr, FRAME_SEED)
+    d_llr = torch.from_numpy(llr).to(dev)
+    d_syn = met.syndrome(code, torch.from_numpy(bits).to(dev))
+    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters) + 256, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
+                          check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
+
+    ms, kt, out = timed(step, args.steps, args.warmup)
+    value = B * n * args.steps / (ms * 1e-3) / 1e6
+    W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 64
+    early = not args.fixed_iters
+    cls, var = job_bytes(code, out.iterations.cpu().numpy(), out.converged.cpu().numpy(), max_iter, early, W)
+    classes = [c for c in code.classes() if c["n_msg"] >= 0]
+    dom = max(classes, key=lambda c: c["n_checks"] * (c["n_msg"] + c["n_leaf"]))
+    kname = "k_check<%d,%d>" % (dom["n_msg"], dom["n_leaf"])
+    wl = "%s N=%d B=%d snr=%g max_iter=%d %s" % (prof, n, B, snr, max_iter, "early-exit" if early else "fixed")
+    kl, kms = kt.get(kname, (0, 0.0))
+    rec = {
+        "value": round(value, 3),
+        "ms_per_step": round(ms / args.steps, 3),
+        "config": {
+            "workload": "plain BP (one decode call per batch), rate %s MET profile, N=%d, %d frames, SNR %g, "
+            "max %d iterations, %s" % (PROFILES[prof].rate, n, B, snr, max_iter,
+                                     "per-frame early exit" if early else "fixed iterations"),
+            "profile": prof, "N": n, "frames": B, "snr": snr, "max_iter": max_iter, "mode": "plain",
+            "interleave": W, "code_seed": CODE_SEED[prof], "frame_seed": FRAME_SEED,
+        },
+        "roofline": roofline(kname, cls[kname] * args.steps, kl, kms, measured_traffic(kname, wl)),
+        "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)} for k, v in kt.items()},
+    }
+    rec.update(fer_summary(out, bits))
+    return rec
 
 
 def main() -> int:
@@ -154,16 +423,18 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--profile", default="r0.1", choices=sorted(PROFILES))
+    ap.add_argument("--workload", default="mix", choices=("mix", "single"))
+    ap.add_argument("--profile", default="r0.1", choices=sorted(PROFILES), help="code of --workload single")
     ap.add_argument("--n", type=int, default=10**6)
-    ap.add_argument("--frames", type=int, default=64)
-    ap.add_argument("--snr", type=float, default=None)
-    ap.add_argument("--max-iter", type=int, default=None)
+    ap.add_argument("--frames", type=int, default=64, help="frames (per job for the mix)")
+    ap.add_argument("--snr", type=float, default=None, help="override every job's SNR")
+    ap.add_argument("--max-iter", type=int, default=None, help="override every job's budget")
     ap.add_argument("--fixed-iters", action="store_true")
-    ap.add_argument("--check-steps", type=int, default=0, help="check-kernel steps per wave (0 = default)")
+    ap.add_argument("--check-steps", type=int, default=0, help="check steps per wave (0 = default)")
     ap.add_argument("--vn-chunk", type=int, default=0, help="variable-kernel gathers in flight (0 = default)")
+    ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=40, help="iterations per frame in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=20, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (scale for rocprofv3 byte counters)")
@@ -185,136 +456,37 @@ def main() -> int:
         print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 5}))
         return 0
 
-    prof = args.profile
-    snr = args.snr if args.snr is not None else BJ_SNR[prof]
-    max_iter = args.max_iter if args.max_iter is not None else ITER_BUDGET[prof]
-    n, B = args.n, args.frames
-
+    if args.workload == "mix":
+        cpu_jobs = [(p, args.frames, args.max_iter or ITER_BUDGET[p]) for p in MIX]
+    else:
+        cpu_jobs = [(args.profile, args.frames, args.max_iter or ITER_BUDGET[args.profile])]
     cpu = None
     if not args.no_cpu_baseline:
         # before any GPU initialisation: the oracle runs in forked host processes
-        cpu = cpu_baseline(prof, n, snr, max_iter, min(args.cpu_iters, max_iter), args.cpu_workers)
+        cpu = cpu_baseline(cpu_jobs, args.n, args.snr, min(args.cpu_iters, min(b for _, _, b in cpu_jobs)),
+                           args.cpu_workers)
 
-    import numpy as np
-    import torch
-
-    import paper_1711_01783_amd as met
-
-    dev = torch.device("cuda:0")
-    code = met.Code.build(PROFILES[prof], n, CODE_SEED[prof])
-    st = code.info()
-    bits, llr = make_frames(n, B, snr, FRAME_SEED)
-    d_llr = torch.from_numpy(llr).to(dev)
-    d_bits = torch.from_numpy(bits).to(dev)
-    d_syn = met.syndrome(code, d_bits)
-    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters) + 256, dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-
-    out = None
-    for _ in range(args.warmup):
-        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
-                         check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
-    torch.cuda.synchronize()
-
-    met.timing_enable(True)
-    met.timing_collect()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        out = met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
-                         check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
-    stop.record()
-    torch.cuda.synchronize()
-    elapsed_ms = start.elapsed_time(stop)
-    ktimes = met.timing_collect()
-    met.timing_enable(False)
-
-    ms_per_step = elapsed_ms / args.steps
-    value = B * n * args.steps / (elapsed_ms * 1e-3) / 1e6
-
-    iters = out.iterations.cpu().numpy()
-    conv = out.converged.cpu().numpy()
-    dec = out.bits.cpu().numpy()
-    frame_err = np.any(dec != bits, axis=1)
-    nerr = int(frame_err.sum())
-    lo, hi = wilson(nerr, B)
-
-    # Algorithmic bytes of the dominant check kernel over the timed region:
-    # frames still running in launch l of a step; a frame that converged at
-    # iteration r takes part in launches 1 .. r+1 (launch r+1 runs its test).
-    W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 64
-    classes = code.classes()
-    dom = max((c for c in classes if c["n_msg"] >= 0), key=lambda c: c["n_checks"] * (c["n_msg"] + c["n_leaf"]))
-    kname = "k_check<%d,%d>" % (dom["n_msg"], dom["n_leaf"])
-    last = np.where(conv == 1, np.minimum(iters + 1, max_iter), max_iter)
-    cn_bytes = 0.0
-    for l in range(1, max_iter + 1):
-        frames_l = int(np.count_nonzero(last >= l))
-        cn_bytes += frames_l * class_bytes_per_frame(dom, W, first=(l == 1), test=(l >= 2 and not args.fixed_iters))
-    cn_bytes *= args.steps
-    launches, cn_ms = ktimes.get(kname, (0, 0.0))
-    cn_avg_ms = cn_ms / max(1, launches)
-    bytes_per_launch = cn_bytes / max(1, launches)
-    achieved = bytes_per_launch / (cn_avg_ms * 1e-3) / 1e9 if cn_avg_ms > 0 else 0.0
-    workload_key = "%s N=%d B=%d snr=%g max_iter=%d %s" % (
-        prof, n, B, snr, max_iter, "fixed" if args.fixed_iters else "early-exit")
-    traffic = measured_traffic(workload_key)
-    iter_ms = sum(v[1] for k, v in ktimes.items() if k.startswith("k_check") or k == "k_variable")
-    iter_bytes = args.steps * max_iter * B * (check_bytes_per_frame(classes, W) + variable_bytes_per_frame(
-        code.info(), W))
-
+    body = run_mix(args, cpu) if args.workload == "mix" else run_single(args, cpu)
     rec = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": body.pop("value"),
         "unit": "Mbit/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": body.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic: seeded uniform bits, BPSK over AWGN, FP32 LLRs; seeded random MET code",
-        "config": {
-            "workload": "plain BP (one decode call per batch), rate %s MET profile, N=%d, %d frames, SNR %g, "
-            "max %d iterations, %s" % (PROFILES[prof].rate, n, B, snr, max_iter,
-                                     "fixed iterations" if args.fixed_iters else "per-frame early exit"),
-            "profile": prof,
-            "N": n,
-            "frames": B,
-            "snr": snr,
-            "max_iter": max_iter,
-            "mode": "plain",
-            "interleave": W,
-            "code_seed": CODE_SEED[prof],
-            "frame_seed": FRAME_SEED,
-        },
-        "roofline": {
-            "kernel": kname,
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": round(bytes_per_launch),
-            "avg_launch_us": round(cn_avg_ms * 1e3, 2),
-        },
+        "data": "synthetic: seeded uniform bits, BPSK over AWGN, FP32 LLRs; seeded random MET codes",
+        "config": body.pop("config"),
+        "roofline": body.pop("roofline"),
         "cpu_baseline": cpu,
-        "fer": round(nerr / B, 4),
-        "fer_ci95": [round(lo, 4), round(hi, 4)],
-        "converged_frames": int(conv.sum()),
-        "mean_iterations": round(float(iters.mean()), 2),
-        "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)} for k, v in ktimes.items()},
-        "bytes_per_frame_iteration": {
-            "check": check_bytes_per_frame(classes, W),
-            "variable": variable_bytes_per_frame(st, W),
-        },
-        "iteration_kernels_gbs": round(iter_bytes / (iter_ms * 1e-3) / 1e9, 1) if iter_ms > 0 else None,
-        "tuning": {"check_steps_per_wave": args.check_steps, "variable_chunk": args.vn_chunk},
     }
+    rec.update(body)
+    rec["tuning"] = {"check_steps_per_wave": args.check_steps, "variable_chunk": args.vn_chunk,
+                     "blocks_per_cu": args.blocks_per_cu}
     print(json.dumps(rec), flush=True)
     return 0
 

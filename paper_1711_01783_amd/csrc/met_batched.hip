@@ -34,25 +34,70 @@ struct BatchJob {
   int64_t leaf_words;
 };
 
+// Control block at the start of the workspace: grid-barrier state, the
+// barrier's group counters and the per-phase tile counters.  Every counter
+// sits on its own 128-byte line.
 struct BarrierState {
   uint32_t count, gen;
   int32_t err, pad;
 };
 
+constexpr int kLine = 32;                     // uint32 words per 128-byte line
+constexpr int kXcds = 8;                      // blocks are placed on XCD (block id mod 8)
+constexpr int kMaxBarrierGroups = 64;         // groups of at most 32 blocks of one XCD
+constexpr int kMaxJobs = 64;
+constexpr int kCounterSets = 3;               // tile counters rotate over phases
+constexpr size_t kOffGroups = 256;
+constexpr size_t kOffTiles = kOffGroups + (size_t)kMaxBarrierGroups * kLine * 4;
+constexpr size_t kControlBytes = kOffTiles + (size_t)kCounterSets * kMaxJobs * kXcds * kLine * 4;
+constexpr int kMaxGrid = 32 * kXcds * (kMaxBarrierGroups / kXcds);  // 2048 blocks
+
 constexpr uint32_t kSpinLimit = 1u << 22;  // polls of about 0.1 us each
 
-__device__ void grid_barrier(BarrierState *b, uint32_t nblocks) {
-  __threadfence();  // release this thread's global writes at device scope
+__device__ __forceinline__ uint32_t *group_counter(char *ctl, int g) {
+  return reinterpret_cast<uint32_t *>(ctl + kOffGroups) + (size_t)g * kLine;
+}
+
+__device__ __forceinline__ uint32_t *tile_counter(char *ctl, int set, int job, int xcd) {
+  return reinterpret_cast<uint32_t *>(ctl + kOffTiles) + ((size_t)(set * kMaxJobs + job) * kXcds + xcd) * kLine;
+}
+
+// Grid-wide barrier in two levels: the blocks of one XCD count in groups of
+// at most 32 on their own line, and the last arriver of each group counts at
+// the top; the last group flips the generation that everyone polls.  Cache
+// maintenance is kept to what the hand-over needs: each wave waits for its own
+// stores, one thread per block writes the compute unit's stores back to
+// device scope (release) and, after the flip, invalidates its caches
+// (acquire), which the block's other waves, held at the block barrier, share.
+// The wait is bounded; on expiry the error flag is set, every later barrier
+// returns at once and the caller stops.  Returns the error flag.
+__device__ int grid_barrier(char *ctl, uint32_t nblocks) {
+  __shared__ int s_err;
+  BarrierState *b = reinterpret_cast<BarrierState *>(ctl);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t gen0 = __hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
+    const uint32_t xcd = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+    const uint32_t nx = (nblocks - xcd + kXcds - 1) / kXcds;  // blocks on this XCD
+    const uint32_t gsz = min(32u, nx - (k & ~31u));
+    uint32_t ngroups = 0;
+    for (uint32_t x = 0; x < kXcds && x < nblocks; ++x) ngroups += ((nblocks - x + kXcds - 1) / kXcds + 31) / 32;
+    uint32_t *gc = group_counter(ctl, (int)((k / 32) * kXcds + xcd));
+    const uint32_t gen0 = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    bool last = false;
+    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsz - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == ngroups - 1;
+    }
+    if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
-      while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
         if (__hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         if (++spins == kSpinLimit) {
           __hip_atomic_store(&b->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -61,27 +106,42 @@ __device__ void grid_barrier(BarrierState *b, uint32_t nblocks) {
         __builtin_amdgcn_s_sleep(2);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_err = __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
-  __threadfence();  // acquire: see every block's writes of the previous phase
+  return s_err;
 }
+
+// The job table is read through the constant address space: it is written
+// before the launch and never during it, so its fields come in as wide scalar
+// loads into scalar registers.
+#if defined(__HIP_DEVICE_COMPILE__)
+using CJob = const __attribute__((address_space(4))) BatchJob;
+#else
+using CJob = const BatchJob;  // the host pass only parses device code
+#endif
 
 // Check tile t of job j at iteration l.
 template <int IPW, bool GEN>
-__device__ __forceinline__ void check_tile(const BatchJob &jb, int l, int64_t t) {
-  const int64_t g = t / jb.cn_tiles;
-  int64_t r = t % jb.cn_tiles;
+__device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) {
+  const int32_t cn_tiles = jobs[j].cn_tiles;
+  const int64_t g = t / cn_tiles;
+  int64_t r = t % cn_tiles;
   int c = 0;
-  while (r >= jb.cls_blocks[c]) r -= jb.cls_blocks[c++];
-  CheckParams p = jb.cp;
+  while (r >= jobs[j].cls_blocks[c]) r -= jobs[j].cls_blocks[c++];
+  CheckParams p = jobs[j].cp;
+  const int64_t lw = jobs[j].leaf_words;
+  uint64_t *B1 = jobs[j].B1, *unsat = jobs[j].unsat;
+  const int32_t G = jobs[j].G;
   p.it = l;
-  p.flags = jb.early && l >= 2 ? F_TEST : 0;
-  p.Pin = l == 1 ? jb.L2 : jb.P;
-  p.B1in = jb.B1 + (size_t)((l - 1) & 1) * jb.leaf_words;
-  p.B1out = jb.B1 + (size_t)(l & 1) * jb.leaf_words;
-  p.unsat = jb.unsat + (size_t)((l - 1) & 1) * jb.G;
-  p.unsat_clear = c == 0 ? jb.unsat + (size_t)(l & 1) * jb.G : nullptr;
-  const ClassArgs &a = jb.cls[c];
+  p.flags = jobs[j].early && l >= 2 ? F_TEST : 0;
+  p.Pin = l == 1 ? jobs[j].L2 : jobs[j].P;
+  p.B1in = B1 + (size_t)((l - 1) & 1) * lw;
+  p.B1out = B1 + (size_t)(l & 1) * lw;
+  p.unsat = unsat + (size_t)((l - 1) & 1) * G;
+  p.unsat_clear = c == 0 ? unsat + (size_t)(l & 1) * G : nullptr;
+  const ClassArgs a = jobs[j].cls[c];
   constexpr int I2 = IPW > 2 ? 2 : IPW;  // degree-11/12 checks: at most 2 steps
   const int gi = (int)g;
   // One compiled mode: c2v starts zero-filled, so iteration 1 needs no variant.
@@ -98,49 +158,141 @@ __device__ __forceinline__ void check_tile(const BatchJob &jb, int l, int64_t t)
   }
 }
 
-__device__ __forceinline__ void variable_tile(const BatchJob &jb, int l, int64_t t) {
-  VarParams vp = jb.vp;
+__device__ __forceinline__ void variable_tile(CJob *jobs, int j, int l, int64_t t) {
+  VarParams vp = jobs[j].vp;
+  const int32_t vb = jobs[j].vn_blocks;
   vp.it = l;
-  vp.retire = jb.early && l >= 2;
-  vp.unsat = jb.unsat + (size_t)((l - 1) & 1) * jb.G;
-  variable_body<kBatchW, 16, true>(vp, t % jb.vn_blocks, (int)(t / jb.vn_blocks));
+  vp.retire = jobs[j].early && l >= 2;
+  vp.unsat = jobs[j].unsat + (size_t)((l - 1) & 1) * jobs[j].G;
+  variable_body<kBatchW, 16, true>(vp, t % vb, (int)(t / vb));
 }
 
 // Phase step of job j: s = phase - offset; even s: check update of iteration
 // s/2 + 1, odd s: its variable update; nothing outside [0, 2 max_iter).
-__device__ __forceinline__ int64_t job_tiles(const BatchJob &jb, int phase, int *l, int *kind) {
-  const int s = phase - jb.offset;
-  if (s < 0 || s >= 2 * jb.max_iter) return 0;
+__device__ __forceinline__ int64_t job_tiles(CJob *jobs, int j, int phase, int *l, int *kind) {
+  const int s = phase - jobs[j].offset;
+  if (s < 0 || s >= 2 * jobs[j].max_iter) return 0;
   *l = s / 2 + 1;
   *kind = s & 1;
-  return *kind == 0 ? (int64_t)jb.cn_tiles * jb.G : (int64_t)jb.vn_blocks * jb.G;
+  return (int64_t)(*kind == 0 ? jobs[j].cn_tiles : jobs[j].vn_blocks) * jobs[j].G;
 }
 
-// The register budget is capped for 6 resident waves per SIMD: the launch
-// mixes memory-bound variable tiles that need many waves in flight.  Run-time
-// degree checks (GEN) are compiled only into the variant used by batches that
-// hold such classes, which keeps their register arrays out of the common one.
+// Next job (from *cur, round-robin) that has tiles this phase and is not yet
+// exhausted on this XCD; its tile range on this XCD is [lo, hi).  Tiles of a
+// job's phase are split into one contiguous range per XCD.
+__device__ bool next_range(CJob *jobs, int n_jobs, int phase, int xcd, int *cur, uint64_t *done, int *j,
+                           int64_t *lo, int64_t *hi) {
+  for (int k = 0; k < n_jobs; ++k) {
+    int jj = *cur + k;
+    if (jj >= n_jobs) jj -= n_jobs;
+    if ((*done >> jj) & 1ull) continue;
+    int l = 0, kind = 0;
+    const int64_t n = job_tiles(jobs, jj, phase, &l, &kind);
+    const int64_t a = n * xcd / kXcds, b = n * (xcd + 1) / kXcds;
+    if (b > a) {
+      *j = jj;
+      *lo = a;
+      *hi = b;
+      *cur = jj + 1 == n_jobs ? 0 : jj + 1;
+      return true;
+    }
+    *done |= 1ull << jj;
+  }
+  return false;
+}
+
+// Atomic add by lane 0 of the calling wave, result broadcast to the wave.
+__device__ __forceinline__ uint32_t wave_fetch_inc(uint32_t *c) {
+  uint32_t v = 0;
+  if ((threadIdx.x & 63) == 0) v = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Claims the next tile for the block (wave 0 of the block, wave-uniformly):
+// -1 when every job's range on this XCD is exhausted for the phase.
+__device__ int64_t claim(CJob *jobs, int n_jobs, int phase, int xcd, char *ctl, int *cur, uint64_t *done, int *j) {
+  int64_t lo = 0, hi = 0;
+  while (next_range(jobs, n_jobs, phase, xcd, cur, done, j, &lo, &hi)) {
+    const uint32_t v = wave_fetch_inc(tile_counter(ctl, phase % kCounterSets, *j, xcd));
+    if (lo + (int64_t)v < hi) return lo + v;
+    *done |= 1ull << *j;
+  }
+  return -1;
+}
+
+// One launch runs every phase of every job.  Within a phase, blocks claim
+// tiles dynamically from per-(job, XCD) counters, alternating between jobs, so
+// blocks that the hardware schedules faster take more tiles and all finish
+// together; the claim for the next tile is issued before the current tile's
+// loads.  The register budget is capped for 6 resident waves per SIMD.
+// Run-time-degree checks (GEN) are compiled only into the variant used by
+// batches that hold such classes, which keeps their register arrays out of
+// the common one.
 template <int IPW, bool GEN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_persistent(
-    const BatchJob *jobs, int n_jobs, int n_phases, BarrierState *bar) {
+    const BatchJob *table, int n_jobs, int n_phases, char *ctl) {
+  CJob *jobs = (CJob *)table;
+  __shared__ int s_job[2];
+  __shared__ int64_t s_tile[2];
+  const int xcd = (int)(blockIdx.x % kXcds);
+  int cur = (int)((blockIdx.x / kXcds) % n_jobs);  // claim state of wave 0
   for (int phase = 0; phase < n_phases; ++phase) {
-    for (int64_t round = 0;; ++round) {
-      bool any = false;
-      const int64_t t = round * gridDim.x + blockIdx.x;
-      for (int j = 0; j < n_jobs; ++j) {
-        const BatchJob &jb = jobs[j];
-        int l = 0, kind = 0;
-        const int64_t n = job_tiles(jb, phase, &l, &kind);
-        if (t >= n) continue;
-        any = true;
-        if (kind == 0)
-          check_tile<IPW, GEN>(jb, l, t);
-        else
-          variable_tile(jb, l, t);
-      }
-      if (!any) break;
+    if (blockIdx.x == 0) {  // counters of the phase after this one (last used two phases ago)
+      const int nxt = (phase + 1) % kCounterSets;
+      for (int i = threadIdx.x; i < n_jobs * kXcds; i += kBlock)
+        __hip_atomic_store(tile_counter(ctl, nxt, i / kXcds, i % kXcds), 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_barrier(bar, gridDim.x);
+    uint64_t done = 0;
+    const bool leader = wave_id() == 0;  // wave 0 claims tiles for the block
+    if (leader) {
+      int j = -1;
+      const int64_t t = claim(jobs, n_jobs, phase, xcd, ctl, &cur, &done, &j);
+      if ((threadIdx.x & 63) == 0) {
+        s_job[0] = t >= 0 ? j : -1;
+        s_tile[0] = t;
+      }
+    }
+    __syncthreads();
+    for (int k = 0;; k ^= 1) {
+      const int j = __builtin_amdgcn_readfirstlane(s_job[k]);
+      if (j < 0) break;
+      const int64_t t = uniform64(s_tile[k]);
+      int pj = -1;
+      int64_t plo = 0, phi = 0;
+      uint32_t pv = 0;
+      if (leader && next_range(jobs, n_jobs, phase, xcd, &cur, &done, &pj, &plo, &phi))
+        pv = wave_fetch_inc(tile_counter(ctl, phase % kCounterSets, pj, xcd));
+      int l = 0, kind = 0;
+      (void)job_tiles(jobs, j, phase, &l, &kind);
+      if (kind == 0)
+        check_tile<IPW, GEN>(jobs, j, l, t);
+      else
+        variable_tile(jobs, j, l, t);
+      if (leader) {
+        int64_t nt = -1;
+        if (pj >= 0) {
+          if (plo + (int64_t)pv < phi) {
+            nt = plo + pv;
+          } else {
+            done |= 1ull << pj;
+            nt = claim(jobs, n_jobs, phase, xcd, ctl, &cur, &done, &pj);
+          }
+        }
+        if ((threadIdx.x & 63) == 0) {
+          s_job[k ^ 1] = nt >= 0 ? pj : -1;
+          s_tile[k ^ 1] = nt;
+        }
+      }
+      __syncthreads();
+    }
+    if (grid_barrier(ctl, gridDim.x)) return;  // barrier expired: results are invalid, stop
   }
 }
 
@@ -148,13 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_floats(float *x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) x[i] = 0.0f;
 }
 
-__global__ void k_barrier_init(BarrierState *b) {
-  if (threadIdx.x == 0) {
-    b->count = 0;
-    b->gen = 0;
-    b->err = 0;
-    b->pad = 0;
-  }
+__global__ __launch_bounds__(kBlock) void k_control_init(uint32_t *ctl) {
+  for (size_t i = threadIdx.x; i < kControlBytes / 4; i += kBlock) ctl[i] = 0u;
 }
 
 // ----------------------------------------------------------------------------
@@ -170,7 +317,7 @@ BatchLayout make_batch_layout(const met_job *jobs, int n) {
   BatchLayout L;
   size_t o = 0;
   L.off_barrier = o;
-  o += 256;
+  o += align256(kControlBytes);
   L.off_table = o;
   o += align256(sizeof(BatchJob) * (size_t)n);
   for (int j = 0; j < n; ++j) {
@@ -319,8 +466,8 @@ struct Batched {
     const void *kfn = kernel();
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kfn, kBlock, 0));
     if (occ < 1) return fail(MET_EHIP, "persistent kernel cannot be resident");
-    const int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : occ;
-    grid = (unsigned)(per_cu * cus);
+    const int per_cu = blocks_per_cu > 0 ? std::min(blocks_per_cu, occ) : std::min(occ, 6);
+    grid = (unsigned)std::min(per_cu * cus, kMaxGrid);
     return MET_OK;
   }
 
@@ -369,12 +516,12 @@ struct Batched {
         hipLaunchKernelGGL(k_zero_floats, dim3((unsigned)std::min<int64_t>(8192, (nc + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, st, reinterpret_cast<float *>(ws + L.off_job[j] + pl.off_c2v), nc);
     }
-    BarrierState *bar = reinterpret_cast<BarrierState *>(ws + L.off_barrier);
+    char *ctl = ws + L.off_barrier;
     const BatchJob *tab = reinterpret_cast<const BatchJob *>(ws + L.off_table);
-    hipLaunchKernelGGL(k_barrier_init, dim3(1), dim3(64), 0, st, bar);
+    hipLaunchKernelGGL(k_control_init, dim3(1), dim3(kBlock), 0, st, reinterpret_cast<uint32_t *>(ctl));
     {
       ScopedTimer t(st, "k_persistent");
-      void *args[] = {(void *)&tab, (void *)&n, (void *)&n_phases, (void *)&bar};
+      void *args[] = {(void *)&tab, (void *)&n, (void *)&n_phases, (void *)&ctl};
       (void)hipLaunchKernel(kernel(), dim3(grid), dim3(kBlock), args, 0, st);
     }
     for (int j = 0; j < n; ++j) {

@@ -186,11 +186,23 @@ __device__ __forceinline__ void clear_next_unsat(const CheckParams &p, int64_t b
 }
 
 // Loads of words that an earlier phase of the same persistent launch may have
-// written: vector loads at device scope (never the scalar cache).
+// written.  The phase barrier orders those writes before this load, so a plain
+// vector load sees them; the scalar cache, which no barrier invalidates, must
+// not be used (the launch stores to these buffers, so the compiler keeps such
+// loads in the vector path).  Outside persistent launches the words are
+// constant for the kernel and go through the scalar cache.
 template <bool PERSIST>
 __device__ __forceinline__ uint64_t ld_word(const uint64_t *p, int64_t i) {
-  if (PERSIST) return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (PERSIST) return p[i];
   return ldro(p, i);
+}
+
+// Load of a word that another block may write in the same phase (the frame
+// mask during retirement): a device-scope atomic load.
+template <bool PERSIST>
+__device__ __forceinline__ uint64_t ld_racy(const uint64_t *p, int64_t i) {
+  if (PERSIST) return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return p[i];
 }
 
 // Check update of one class of checks with a compile-time shape (NM message
@@ -201,7 +213,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
   constexpr int D = NM + NL;
   constexpr int IPWAVE = 64 / W;
   clear_next_unsat(p, bx, g);
-  const uint64_t act = PERSIST ? ld_word<true>(p.active, g) : p.active[g];
+  const uint64_t act = p.active[g];  // not written during check updates
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int w = lane % W, q = lane / W;
@@ -319,7 +331,7 @@ template <int W, bool PERSIST>
 __device__ __forceinline__ void check_generic_body(const CheckParams &p, const ClassArgs &c, int64_t bx, int g) {
   constexpr int D = MET_MAX_CHECK_DEGREE;
   clear_next_unsat(p, bx, g);
-  const uint64_t act = PERSIST ? ld_word<true>(p.active, g) : p.active[g];
+  const uint64_t act = p.active[g];  // not written during check updates
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int w = lane % W, q = lane / W;
@@ -469,14 +481,14 @@ struct VarParams {
 // at a time, summed in list order).
 template <int W, int U, bool PERSIST>
 __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, int g) {
-  uint64_t act = PERSIST ? ld_word<true>(p.active, g) : p.active[g];
+  uint64_t act = ld_racy<PERSIST>(p.active, g);
   if (p.retire) {
     // Frames whose test of iteration it-1 passed stop here; their P stays at
     // iteration it-1.  Block (0,0) records the outcome for every group.
     if (bx == 0 && g == 0) {
       for (int gg = threadIdx.x; gg < p.G; gg += kBlock) {
-        const uint64_t a = PERSIST ? ld_word<true>(p.active, gg) : p.active[gg];
-        const uint64_t u = PERSIST ? ld_word<true>(p.unsat, gg) : p.unsat[gg];
+        const uint64_t a = p.active[gg];  // only this block writes the mask
+        const uint64_t u = p.unsat[gg];
         const uint64_t done = a & ~u;
         if (done) {
           for (int w = 0; w < W; ++w)
@@ -489,7 +501,7 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
         }
       }
     }
-    act &= PERSIST ? ld_word<true>(p.unsat, g) : p.unsat[g];
+    act &= p.unsat[g];
   }
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id(), w = lane % W, q = lane / W;
