@@ -307,6 +307,9 @@ def run_mix(args, cpu) -> dict:
     p_ms, p_kt, p_out = timed(plain, args.steps, args.warmup)
     del wss
     dec = met.BatchedDecoder(check_steps_per_wave=args.check_steps, blocks_per_cu=args.blocks_per_cu)
+    shape = None
+    if not args.no_autotune and not args.check_steps and not args.blocks_per_cu:
+        shape = dec.autotune(jobs)  # outside the timed region
     b_ms, b_kt, b_out = timed(lambda: dec(jobs), args.steps, args.warmup)
     expired = dec.barrier_expired()
     # per-launch timing runs the launch sequence outside a graph; the same steps
@@ -362,6 +365,7 @@ def run_mix(args, cpu) -> dict:
         "graph_replay": {"value": round(total_bits / (g_ms * 1e-3) / 1e6, 3),
                          "ms_per_step": round(g_ms / args.steps, 3)},
         "identical_outputs": bool(same),
+        "autotuned_shape": shape,
         "barrier_expired": bool(expired),
         "jobs": per_job,
         "bytes_per_step": {"check": check_bytes, "variable": var_bytes},
@@ -418,12 +422,145 @@ def run_single(args, cpu) -> dict:
     return rec
 
 
+def _wbp_setup(prof: str, n: int, B: int, snr: float, seed: int):
+    import torch
+
+    import paper_1711_01783_amd as met
+
+    code = met.Code.build(PROFILES[prof], n, CODE_SEED[prof])
+    bits, llr = make_frames(n, B, snr, seed)
+    d_bits = torch.from_numpy(bits).to("cuda:0")
+    syn = met.syndrome(code, d_bits)
+    sgn = 1.0 - 2.0 * d_bits.float()
+    return code, torch.from_numpy(llr).to("cuda:0"), syn, sgn
+
+
+def run_wbp_train(args) -> dict:
+    """Weighted-BP training steps: forward (L unrolled iterations, states kept
+    every k-th), BCE loss, hand-written adjoint, Adam update of the [T, L]
+    scales.  Batches rotate over a few resident ones."""
+    import torch
+
+    from paper_1711_01783_amd import wbp
+
+    prof, n, B = args.profile, args.n, args.frames
+    L, k = args.iters, args.ckpt
+    snr = args.snr if args.snr is not None else BJ_SNR[prof]
+    batches = [_wbp_setup(prof, n, B, snr, FRAME_SEED + 1000 * r) for r in range(4)]
+    code = batches[0][0]
+    T = code.info()["n_edge_types"]
+    w = torch.ones(T, L, device="cuda:0", requires_grad=True)
+    opt = torch.optim.Adam([w], lr=args.lr)
+    losses = []
+
+    def step(r=[0]):
+        _, llr, syn, sgn = batches[r[0] % len(batches)]
+        r[0] += 1
+        opt.zero_grad(set_to_none=True)
+        post = wbp.weighted_bp(w, batches[0][0], llr, syn, k)
+        loss = torch.nn.functional.softplus(-sgn * post).mean()
+        loss.backward()
+        opt.step()
+        losses.append(loss.detach())
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = timed_plain(step, args.steps)
+    hist = [float(x) for x in losses]
+    return {
+        "metric": "weighted-BP training: decoded Mbit/s (forward + adjoint + update per step)",
+        "value": round(B * n * args.steps / (ms * 1e-3) / 1e6, 3) if ms > 0 else None,
+        "unit": "Mbit/s",
+        "ms_per_step": round(ms / args.steps, 3),
+        "config": {"workload": "weighted BP training, rate %s MET profile, N=%d, %d frames per step, %d unrolled "
+                               "iterations, checkpoint every %d, SNR %g, Adam lr %g, scales initialised to 1"
+                               % (PROFILES[prof].rate, n, B, L, k, snr, args.lr),
+                   "profile": prof, "N": n, "frames": B, "iterations": L, "ckpt_every": k, "snr": snr},
+        "loss_first": round(hist[0], 6), "loss_last": round(hist[-1], 6),
+        "workspace_bytes": wbp.workspace_bytes(code, B, L, k),
+    }
+
+
+def run_wbp_eval(args) -> dict:
+    """Forward + adjoint at full size, a few training steps, then FER of the
+    trained scales against plain BP (fixed iterations, same budget) on fresh
+    frames."""
+    import numpy as np
+    import torch
+
+    import paper_1711_01783_amd as met
+    from paper_1711_01783_amd import wbp
+
+    prof, n, B = args.profile, args.n, args.frames
+    L = args.iters
+    k = args.ckpt or wbp.default_checkpoint_interval(L)
+    snr = args.snr if args.snr is not None else BJ_SNR[prof]
+    code, llr, syn, sgn = _wbp_setup(prof, n, B, snr, FRAME_SEED)
+    T = code.info()["n_edge_types"]
+    w = torch.ones(T, L, device="cuda:0", requires_grad=True)
+    opt = torch.optim.Adam([w], lr=args.lr)
+
+    def step():
+        opt.zero_grad(set_to_none=True)
+        post = wbp.weighted_bp(w, code, llr, syn, k)
+        loss = torch.nn.functional.softplus(-sgn * post).mean()
+        loss.backward()
+        opt.step()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    ms = timed_plain(step, args.steps)
+    # FER on fresh frames: trained scales vs plain BP, same syndromes, L iterations
+    wt = w.detach().contiguous()
+    errs_w = errs_p = conv_w = conv_p = 0
+    total = 0
+    r = 0
+    while total < args.eval_frames:
+        b = min(B, args.eval_frames - total)
+        bits, l2 = make_frames(n, b, snr, FRAME_SEED + 7777, first_frame=total)
+        d_bits = torch.from_numpy(bits).to("cuda:0")
+        s2 = met.syndrome(code, d_bits)
+        d_llr = torch.from_numpy(l2).to("cuda:0")
+        _, bw, cw, _ = wbp.forward(code, d_llr, s2, wt, k)
+        po = met.decode(code, d_llr, s2, L, fixed_iters=True)
+        errs_w += int((bw != d_bits).any(dim=1).sum())
+        errs_p += int((po.bits != d_bits).any(dim=1).sum())
+        conv_w += int(cw.sum())
+        conv_p += int(po.converged.sum())
+        total += b
+        r += 1
+    return {
+        "metric": "weighted-BP forward + adjoint: decoded Mbit/s per training step",
+        "value": round(B * n * args.steps / (ms * 1e-3) / 1e6, 3) if ms > 0 else None,
+        "unit": "Mbit/s",
+        "ms_per_step": round(ms / args.steps, 3),
+        "config": {"workload": "weighted BP forward + adjoint + Adam update, rate %s MET profile, N=%d, %d frames, "
+                               "%d unrolled iterations, checkpoint every %d, SNR %g; then FER of the trained scales vs "
+                               "plain BP (%d fixed iterations) on %d fresh frames"
+                               % (PROFILES[prof].rate, n, B, L, k, snr, L, total),
+                   "profile": prof, "N": n, "frames": B, "iterations": L, "ckpt_every": k, "snr": snr},
+        "workspace_bytes": wbp.workspace_bytes(code, B, L, k),
+        "eval_frames": total,
+        "fer_weighted": round(errs_w / total, 4), "fer_weighted_ci95": [round(x, 4) for x in wilson(errs_w, total)],
+        "fer_plain": round(errs_p / total, 4), "fer_plain_ci95": [round(x, 4) for x in wilson(errs_p, total)],
+        "converged_weighted": conv_w, "converged_plain": conv_p,
+        "training_steps": args.warmup + args.steps + 1,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mix", choices=("mix", "single"))
+    ap.add_argument("--workload", default="mix", choices=("mix", "single", "wbp-train", "wbp-eval"))
+    ap.add_argument("--iters", type=int, default=50, help="weighted BP: unrolled iterations")
+    ap.add_argument("--ckpt", type=int, default=0, help="weighted BP: checkpoint interval (0 = about sqrt)")
+    ap.add_argument("--lr", type=float, default=0.01, help="weighted BP: Adam learning rate")
+    ap.add_argument("--eval-frames", type=int, default=1000, help="wbp-eval: fresh frames for the FER comparison")
     ap.add_argument("--profile", default="r0.1", choices=sorted(PROFILES), help="code of --workload single")
     ap.add_argument("--n", type=int, default=10**6)
     ap.add_argument("--frames", type=int, default=64, help="frames (per job for the mix)")
@@ -433,6 +570,7 @@ def main() -> int:
     ap.add_argument("--check-steps", type=int, default=0, help="check steps per wave (0 = default)")
     ap.add_argument("--vn-chunk", type=int, default=0, help="variable-kernel gathers in flight (0 = default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")
+    ap.add_argument("--no-autotune", action="store_true", help="mix: keep the default persistent launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
@@ -454,6 +592,14 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 5}))
+        return 0
+
+    if args.workload in ("wbp-train", "wbp-eval"):
+        rec = run_wbp_train(args) if args.workload == "wbp-train" else run_wbp_eval(args)
+        rec.update({"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+                    "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                    "data": "synthetic: seeded uniform bits, BPSK over AWGN, FP32 LLRs; seeded random MET code"})
+        print(json.dumps(rec), flush=True)
         return 0
 
     if args.workload == "mix":

@@ -52,6 +52,14 @@ extern "C" {
                                hard decision satisfies its syndrome (Step 5) */
 #define MET_FIXED_ITERS 1u  /* every frame runs max_iter iterations; converged
                                reports the syndrome test after the last one */
+#define MET_NO_COMPACT 2u   /* early exit without compaction: frames that are
+                               still running stay in their groups of 64 (by
+                               default, every 4 iterations, finished frames are
+                               written out and running ones are packed into as
+                               few groups as hold them, when that frees at least
+                               a quarter of the occupied groups; results are
+                               identical either way; no compaction when
+                               posteriors are requested) */
 
 #define MET_MAX_EDGE_TYPES 8
 #define MET_MAX_CHECK_DEGREE 32
@@ -154,7 +162,7 @@ int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int
  *   llr:       dev float32 [B][N], 4-byte aligned
  *   syn:       dev uint8   [B][M]
  *   max_iter:  >= 1
- *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS
+ *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS, optionally | MET_NO_COMPACT
  *   bits:      dev uint8 [B][N] output, hard decisions at each frame's stop
  *   iters:     dev int32 [B] output, iterations run (1..max_iter)
  *   converged: dev uint8 [B] output, 1 iff H bits = syn
@@ -270,6 +278,17 @@ int met_batched_workspace_bytes(const met_job *jobs, int32_t n_jobs, size_t *byt
 int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
                        const met_tuning *tuning, void *stream);
 int met_batched_check(const void *workspace, int32_t *barrier_expired);
+
+/* Autotuner of the batched launch: times candidate launch shapes (check steps
+ * per wave 4/2/1 x resident blocks per compute unit 6..2, then the stagger of
+ * the fastest) on the same jobs with every budget capped at probe_iters
+ * iterations (0 selects 6), discards shapes whose barrier expired, and writes
+ * the fastest to *best (its time per probe run to *best_ms if not NULL).
+ * Synchronises `stream`; overwrites the jobs' outputs.  Results are cached per
+ * device and job signature (code, sizes, budgets, flags) for the life of the
+ * process.  Errors: MET_EINVAL, MET_EHIP. */
+int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
+                         int32_t probe_iters, met_tuning *best, float *best_ms, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *met_last_error(void);

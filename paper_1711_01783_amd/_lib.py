@@ -14,6 +14,7 @@ MET_EHIP = -3
 MET_ESTATE = -4
 MET_EARLY_EXIT = 0
 MET_FIXED_ITERS = 1
+MET_NO_COMPACT = 2
 MET_MAX_EDGE_TYPES = 8
 
 _ERRNAMES = {MET_EINVAL: "MET_EINVAL", MET_ENOMEM: "MET_ENOMEM", MET_EHIP: "MET_EHIP", MET_ESTATE: "MET_ESTATE"}
@@ -107,6 +108,8 @@ def _load():
         "met_batched_workspace_bytes": (ctypes.c_int, [P, i32, ctypes.POINTER(sz)]),
         "met_decode_batched": (ctypes.c_int, [P, i32, P, sz, ctypes.POINTER(met_tuning), P]),
         "met_batched_check": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
+        "met_batched_autotune": (ctypes.c_int, [P, i32, P, sz, i32, ctypes.POINTER(met_tuning),
+                                                ctypes.POINTER(ctypes.c_float), P]),
         "met_timing_enable": (ctypes.c_int, [i32]),
         "met_timing_collect": (ctypes.c_int, [ctypes.POINTER(met_kernel_time), i32, ctypes.POINTER(i32)]),
     }

@@ -6,7 +6,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import (MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER, MET_FIXED_ITERS, check, lib, met_check_class,
+from ._lib import (MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER, MET_FIXED_ITERS, MET_NO_COMPACT, check, lib,
+                   met_check_class,
                    met_code_stats, met_job, met_kernel_time, met_profile, met_tuning)
 
 
@@ -149,11 +150,13 @@ class DecodeOutput:
 
 
 def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, posterior: bool = False,
-           workspace=None, stream=None, check_steps_per_wave: int = 0, variable_chunk: int = 0) -> DecodeOutput:
+           workspace=None, stream=None, check_steps_per_wave: int = 0, variable_chunk: int = 0,
+           compact: bool = True) -> DecodeOutput:
     """Decode llr float32 [B, N] against syn uint8 [B, M] (device tensors).
 
     check_steps_per_wave and variable_chunk (0 = default) select launch shapes
-    of the check and variable kernels; results do not depend on them."""
+    of the check and variable kernels, compact=False keeps running frames in
+    their groups; results do not depend on any of them."""
     import torch
 
     b = int(llr.shape[0])
@@ -176,7 +179,7 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
     check(
         lib.met_decode_ex(
             code.handle, llr.data_ptr(), syn.data_ptr(), b, int(max_iter),
-            MET_FIXED_ITERS if fixed_iters else 0,
+            (MET_FIXED_ITERS if fixed_iters else 0) | (0 if compact else MET_NO_COMPACT),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(),
             None if post is None else post.data_ptr(),
             ctypes.c_void_p(ws_ptr), ws_len, ctypes.byref(tuning), _stream_ptr(stream),
@@ -255,15 +258,43 @@ class BatchedDecoder:
                 outputs.append(DecodeOutput(torch.empty((b, j.code.N), dtype=torch.uint8, device=dev),
                                             torch.empty(b, dtype=torch.int32, device=dev),
                                             torch.empty(b, dtype=torch.uint8, device=dev), None))
-        need = batched_workspace_bytes(jobs)
-        if self.workspace is None or self.workspace.numel() - 256 < need:
-            self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
-            self._ws_ptr = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        self._ensure_workspace(jobs)
         arr = _job_structs(jobs, outputs)
         ws_len = self.workspace.numel() - (self._ws_ptr - self.workspace.data_ptr())
         check(lib.met_decode_batched(arr, len(jobs), ctypes.c_void_p(self._ws_ptr), ws_len,
                                      ctypes.byref(self.tuning), _stream_ptr(stream)))
         return outputs
+
+    def _ensure_workspace(self, jobs):
+        import torch
+
+        need = batched_workspace_bytes(jobs)
+        if self.workspace is None or self.workspace.numel() - 256 < need:
+            self.workspace = torch.empty(need + 256, dtype=torch.uint8, device=jobs[0].llr.device)
+            self._ws_ptr = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+
+    def autotune(self, jobs, probe_iters: int = 0, stream=None) -> dict:
+        """Picks this decoder's launch shape for `jobs` with the library's
+        autotuner (short timed runs of the same jobs; cached per process).
+        Overwrites nothing but scratch outputs; returns the chosen shape."""
+        import torch
+
+        dev = jobs[0].llr.device
+        outs = [DecodeOutput(torch.empty((int(j.llr.shape[0]), j.code.N), dtype=torch.uint8, device=dev),
+                             torch.empty(int(j.llr.shape[0]), dtype=torch.int32, device=dev),
+                             torch.empty(int(j.llr.shape[0]), dtype=torch.uint8, device=dev), None) for j in jobs]
+        self._ensure_workspace(jobs)
+        arr = _job_structs(jobs, outs)
+        best = met_tuning()
+        ms = ctypes.c_float()
+        ws_len = self.workspace.numel() - (self._ws_ptr - self.workspace.data_ptr())
+        check(lib.met_batched_autotune(arr, len(jobs), ctypes.c_void_p(self._ws_ptr), ws_len, int(probe_iters),
+                                       ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)))
+        graph = not (self.tuning.batch_flags & MET_BATCH_NO_GRAPH)
+        self.tuning = best
+        self.tuning.batch_flags = (best.batch_flags & MET_BATCH_NO_STAGGER) | (0 if graph else MET_BATCH_NO_GRAPH)
+        return {"check_steps_per_wave": int(best.check_steps_per_wave), "blocks_per_cu": int(best.blocks_per_cu),
+                "stagger": not (best.batch_flags & MET_BATCH_NO_STAGGER), "probe_ms": float(ms.value)}
 
     def barrier_expired(self) -> bool:
         """True if the last launch's grid barrier timed out (results invalid).

@@ -689,6 +689,135 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
   return b.run();
 }
 
+// ---- Autotuning -------------------------------------------------------------
+// Launch shapes are ranked on a short run of the same jobs (each budget capped
+// at probe_iters iterations): the per-phase cost of a shape is the same in
+// every phase, so a few iterations rank the shapes as the full run would.
+// Results are cached per (device, jobs) signature for the life of the process.
+
+namespace met {
+namespace {
+
+struct TuneEntry {
+  std::vector<uint8_t> key;
+  met_tuning best;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+std::vector<uint8_t> tune_key(const met_job *jobs, int n, int probe_iters) {
+  std::vector<uint8_t> k;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  append_bytes(k, dev);
+  append_bytes(k, probe_iters);
+  for (int j = 0; j < n; ++j) {
+    const met_code *c = jobs[j].code;
+    append_bytes(k, c);
+    append_bytes(k, c->N);
+    append_bytes(k, c->M);
+    append_bytes(k, c->E12);
+    append_bytes(k, jobs[j].B);
+    append_bytes(k, jobs[j].max_iter);
+    append_bytes(k, jobs[j].flags);
+  }
+  return k;
+}
+
+// Time one launch shape: one untimed run, then `reps` runs between events.
+// Returns a negative time if the barrier expired.
+int time_shape(const std::vector<met_job> &probe, char *ws, hipStream_t st, const met_tuning &t, int reps,
+               float *ms) {
+  met_tuning u = t;
+  u.batch_flags |= MET_BATCH_NO_GRAPH;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  int rc = MET_OK;
+  for (int r = 0; r <= reps && rc == MET_OK; ++r) {
+    if (r == 1) rc = hipEventRecord(a, st) == hipSuccess ? MET_OK : fail(MET_EHIP, "hipEventRecord");
+    if (rc == MET_OK) rc = met_decode_batched(probe.data(), (int32_t)probe.size(), ws, SIZE_MAX, &u, st);
+  }
+  if (rc == MET_OK && hipEventRecord(b, st) != hipSuccess) rc = fail(MET_EHIP, "hipEventRecord");
+  if (rc == MET_OK && hipEventSynchronize(b) != hipSuccess) rc = fail(MET_EHIP, "hipEventSynchronize");
+  float t_ms = 0.0f;
+  if (rc == MET_OK && hipEventElapsedTime(&t_ms, a, b) != hipSuccess) rc = fail(MET_EHIP, "hipEventElapsedTime");
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  int32_t expired = 0;
+  rc = met_batched_check(ws, &expired);
+  if (rc) return rc;
+  *ms = expired ? -1.0f : t_ms / (float)reps;
+  return MET_OK;
+}
+
+}  // namespace
+}  // namespace met
+
+extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
+                                    int32_t probe_iters, met_tuning *best, float *best_ms, void *stream) {
+  met::clear_error();
+  int rc = validate_jobs(jobs, n_jobs);
+  if (rc) return rc;
+  if (!best) return fail(MET_EINVAL, "NULL best");
+  if (probe_iters < 0 || probe_iters > 1000) return fail(MET_EINVAL, "probe_iters = %d outside 0..1000", probe_iters);
+  if (probe_iters == 0) probe_iters = 6;
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(MET_EINVAL, "workspace NULL or not 256-byte aligned");
+  const size_t need = met::make_batch_layout(jobs, n_jobs).total;
+  if (ws_bytes < need) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  const std::vector<uint8_t> key = met::tune_key(jobs, n_jobs, probe_iters);
+  {
+    std::lock_guard<std::mutex> lock(met::g_tune_mu);
+    for (const met::TuneEntry &e : met::g_tune)
+      if (e.key == key) {
+        *best = e.best;
+        if (best_ms) *best_ms = e.ms;
+        return MET_OK;
+      }
+  }
+  std::vector<met_job> probe(jobs, jobs + n_jobs);
+  for (met_job &j : probe) j.max_iter = std::min(j.max_iter, probe_iters);
+  char *ws = static_cast<char *>(workspace);
+  const hipStream_t st = (hipStream_t)stream;
+  met_tuning cur{};
+  float cur_ms = -1.0f;
+  // steps per wave x resident blocks per CU, then the stagger of the best
+  for (int ipw : {4, 2, 1})
+    for (int bpc : {6, 5, 4, 3, 2}) {
+      met_tuning t{};
+      t.check_steps_per_wave = ipw;
+      t.blocks_per_cu = bpc;
+      float ms = 0.0f;
+      rc = met::time_shape(probe, ws, st, t, 2, &ms);
+      if (rc) return rc;
+      if (ms > 0.0f && (cur_ms < 0.0f || ms < cur_ms)) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  if (cur_ms < 0.0f) return fail(MET_EHIP, "no launch shape kept its blocks resident");
+  {
+    met_tuning t = cur;
+    t.batch_flags = MET_BATCH_NO_STAGGER;
+    float ms = 0.0f;
+    rc = met::time_shape(probe, ws, st, t, 2, &ms);
+    if (rc) return rc;
+    if (ms > 0.0f && ms < cur_ms) {
+      cur = t;
+      cur_ms = ms;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lock(met::g_tune_mu);
+    met::g_tune.push_back({key, cur, cur_ms});
+  }
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return MET_OK;
+}
+
 extern "C" int met_batched_check(const void *workspace, int32_t *barrier_expired) {
   met::clear_error();
   if (!workspace || !barrier_expired) return fail(MET_EINVAL, "NULL argument");

@@ -34,6 +34,14 @@
 // frames are contiguous (W = 64: one 256-byte row per item, one lane per
 // frame).  Per-item bit words (syndrome, leaf decisions, flags) hold the W
 // frames of a group in one uint64.
+//
+// Compaction (early exit, groups of 64 frames): every few iterations, frames
+// that stopped have their outputs written and their lanes freed; when the
+// frames still running would fill markedly fewer groups than they occupy, they
+// are moved into the fullest groups (all per-frame state: c2v, P, L, leaf
+// inputs, syndrome and the last leaf decisions), so later launches skip the
+// emptied groups.  A frame's arithmetic does not depend on its lane, so the
+// results are identical with and without compaction.
 #include "met_gpu.h"
 
 namespace met {
@@ -41,6 +49,141 @@ namespace met {
 TimingState g_timing;
 
 namespace {
+
+constexpr int kCompactEvery = 4;    // iterations between compaction points
+constexpr int kCompactMinLeft = 4;  // no compaction this close to the budget
+constexpr int kMaxGroups = 1024;    // 65535 frames in groups of 64
+
+struct CompactView {
+  int32_t *n_dest, *dest, *src;  // header, receiving groups, [n_dest][64] source slots
+};
+
+__device__ __forceinline__ CompactView compact_view(int32_t *table, int G) {
+  CompactView v;
+  v.n_dest = table;
+  v.dest = table + 64;
+  v.src = table + 64 + ((G * 4 + 255) & ~255) / 4;  // as compact_table_bytes
+  return v;
+}
+
+// Plans a compaction (one block).  Lanes whose frame stopped running had their
+// outputs written by the flush that precedes this kernel: they are freed.  If
+// the running frames would fit in at least a quarter fewer groups than hold
+// them, the fullest groups become targets and every running frame of the
+// other groups is assigned a free lane of a target; the frame map and the
+// masks are updated here, the state is moved by k_compact_move*.
+__global__ __launch_bounds__(kBlock) void k_compact_plan(uint64_t *active, int32_t *slot_frame, int32_t *table,
+                                                        int G) {
+  __shared__ int32_t cnt[kMaxGroups], order[kMaxGroups];
+  __shared__ int32_t s_targets;
+  const CompactView tv = compact_view(table, G);
+  for (int s = threadIdx.x; s < G * 64; s += kBlock)
+    if (slot_frame[s] >= 0 && !((active[s / 64] >> (s % 64)) & 1ull)) slot_frame[s] = -1;
+  for (int g = threadIdx.x; g < G; g += kBlock) cnt[g] = __popcll(active[g]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int A = 0, Gn = 0;
+    for (int g = 0; g < G; ++g) {
+      A += cnt[g];
+      Gn += cnt[g] > 0;
+    }
+    const int Gt = (A + 63) / 64;
+    int targets = 0;
+    if (Gn - Gt >= max(1, Gn / 4)) {
+      // groups by decreasing count (counting sort; ties by index)
+      int start[66];
+      for (int k = 0; k <= 65; ++k) start[k] = 0;
+      for (int g = 0; g < G; ++g) ++start[64 - cnt[g] + 1];
+      for (int k = 1; k <= 65; ++k) start[k] += start[k - 1];
+      for (int g = 0; g < G; ++g) order[start[64 - cnt[g]]++] = g;
+      targets = Gt;
+    }
+    s_targets = targets;
+    *tv.n_dest = targets;
+  }
+  __syncthreads();
+  const int T = s_targets;
+  if (T == 0) return;
+  for (int i = threadIdx.x; i < T * 64; i += kBlock) tv.src[i] = -1;
+  for (int t = threadIdx.x; t < T; t += kBlock) tv.dest[t] = order[t];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    uint64_t tact = active[order[0]];
+    for (int k = T; k < G; ++k) {
+      const int gs = order[k];
+      uint64_t a = active[gs];
+      while (a) {
+        const int ws = __ffsll((unsigned long long)a) - 1;
+        a &= a - 1;
+        while (tact == ~0ull) {
+          active[order[t]] = tact;
+          tact = active[order[++t]];
+        }
+        const int wt = __ffsll((unsigned long long)~tact) - 1;
+        tact |= 1ull << wt;
+        const int gt = order[t];
+        tv.src[t * 64 + wt] = gs * 64 + ws;
+        slot_frame[gt * 64 + wt] = slot_frame[gs * 64 + ws];
+        slot_frame[gs * 64 + ws] = -1;
+      }
+      active[gs] = 0ull;
+    }
+    active[order[t]] = tact;
+  }
+}
+
+// Moves the W = 64 lanes of float rows [G][items][64] into the receiving groups.
+__global__ __launch_bounds__(kBlock) void k_compact_move(int32_t *table, int G, float *arr, int64_t items) {
+  const CompactView tv = compact_view(table, G);
+  const int t = blockIdx.y;
+  if (t >= *tv.n_dest) return;
+  const int lane = threadIdx.x & 63;
+  const int src = tv.src[t * 64 + lane];
+  if (!__syncthreads_or(src >= 0)) return;
+  const int64_t gt = tv.dest[t], gs = src >> 6, ws = src & 63;
+  for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); i < items;
+       i += (int64_t)gridDim.x * kWavesPerBlock)
+    if (src >= 0) arr[(gt * items + i) * 64 + lane] = arr[(gs * items + i) * 64 + ws];
+}
+
+// Moves bits of per-item words [G][items] (bit w = frame w of the group).
+__global__ __launch_bounds__(kBlock) void k_compact_move_bits(int32_t *table, int G, uint64_t *arr, int64_t items) {
+  __shared__ int32_t in_lane[64], in_src[64];
+  __shared__ int32_t n_in;
+  const CompactView tv = compact_view(table, G);
+  const int t = blockIdx.y;
+  if (t >= *tv.n_dest) return;
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int w = 0; w < 64; ++w) {
+      const int src = tv.src[t * 64 + w];
+      if (src >= 0) {
+        in_lane[n] = w;
+        in_src[n] = src;
+        ++n;
+      }
+    }
+    n_in = n;
+  }
+  __syncthreads();
+  const int n = n_in;
+  if (n == 0) return;
+  const int64_t gt = tv.dest[t];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < items; i += (int64_t)gridDim.x * kBlock) {
+    uint64_t word = arr[gt * items + i];
+    for (int k = 0; k < n; ++k) {
+      const int src = in_src[k];
+      const uint64_t bit = (arr[(int64_t)(src >> 6) * items + i] >> (src & 63)) & 1ull;
+      word = (word & ~(1ull << in_lane[k])) | (bit << in_lane[k]);
+    }
+    arr[gt * items + i] = word;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_slots(int32_t *slot_frame, int B, int GW) {
+  for (int s = blockIdx.x * kBlock + threadIdx.x; s < GW; s += gridDim.x * kBlock) slot_frame[s] = s < B ? s : -1;
+}
 
 struct Decoder {
   const met_code *c;
@@ -140,6 +283,32 @@ struct Decoder {
     const unsigned vn_blocks = (unsigned)((c->N2 + vn_per_block - 1) / vn_per_block);
     const bool early = !(flags & MET_FIXED_ITERS);
     const bool special = post || weights;
+    const bool compact = W == 64 && G > 1 && early && !special && !(flags & MET_NO_COMPACT);
+    int32_t *slot_frame = compact ? at<int32_t>(pl.off_slot) : nullptr;
+    int32_t *ctab = at<int32_t>(pl.off_ctab);
+    vp.slot_frame = slot_frame;
+    if (compact)
+      hipLaunchKernelGGL(k_init_slots, dim3((unsigned)((G * W + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                         slot_frame, B, G * W);
+    FinalParams fp{};
+    fp.vn_slot = d->vn_slot;
+    fp.N = c->N;
+    fp.N2 = c->N2;
+    fp.EL = c->EL;
+    fp.B = B;
+    fp.max_iter = max_iter;
+    fp.P = P;
+    fp.P1a = P1;
+    fp.P1b = P1 ? P1 + leaf_floats : nullptr;
+    fp.B1a = B1;
+    fp.B1b = B1 + leaf_words;
+    fp.active = active;
+    fp.iters = iters;
+    fp.converged = conv;
+    fp.bits = bits;
+    fp.posterior = post;
+    fp.slot_frame = slot_frame;
+    fp.G = G;
     const int base_flags = (post ? F_POST : 0) | (weights ? F_WEIGHTED : 0);
 
     for (int it = 1; it <= max_iter; ++it) {
@@ -169,6 +338,32 @@ struct Decoder {
         else
           hipLaunchKernelGGL((k_variable<W, 8>), grid, dim3(kBlock), 0, st, vp);
       }
+      if (compact && it % kCompactEvery == 0 && max_iter - it >= kCompactMinLeft) {
+        ScopedTimer t(st, "k_compact");
+        // outputs of frames that stopped, then the plan, then the state the
+        // next check update reads: P, c2v, L, leaf inputs, syndrome, and the
+        // leaf decisions of this iteration (tested by the next check update)
+        FinalParams ff = fp;
+        ff.flush = 1;
+        hipLaunchKernelGGL(k_finalize<W>, dim3((unsigned)((c->N + 63) / 64), G), dim3(kBlock), 0, st, ff);
+        hipLaunchKernelGGL(k_compact_plan, dim3(1), dim3(kBlock), 0, st, active, slot_frame, ctab, G);
+        auto move = [&](float *a, int64_t items) {
+          if (items > 0)
+            hipLaunchKernelGGL(k_compact_move, dim3((unsigned)std::min<int64_t>(2048, (items + 3) / 4), G),
+                               dim3(kBlock), 0, st, ctab, G, a, items);
+        };
+        auto move_bits = [&](uint64_t *a, int64_t items) {
+          if (items > 0)
+            hipLaunchKernelGGL(k_compact_move_bits, dim3((unsigned)std::min<int64_t>(1024, (items + 255) / 256), G),
+                               dim3(kBlock), 0, st, ctab, G, a, items);
+        };
+        move(c2v, c->E12);
+        move(P, c->N2);
+        move(L2, c->N2);
+        move(Lphi, c->EL);
+        move_bits(synw, c->M);
+        move_bits(B1 + (size_t)(it & 1) * leaf_words, c->EL);
+      }
     }
     TestParams tp{};
     tp.edge_msgvn = d->edge_msgvn;
@@ -188,25 +383,7 @@ struct Decoder {
       ScopedTimer t(st, "k_test");
       hipLaunchKernelGGL(k_test<W>, dim3((unsigned)((c->M + per - 1) / per), G), dim3(kBlock), 0, st, tp);
     }
-    FinalParams fp{};
-    fp.vn_slot = d->vn_slot;
-    fp.N = c->N;
-    fp.N2 = c->N2;
-    fp.EL = c->EL;
-    fp.B = B;
-    fp.max_iter = max_iter;
-    fp.P = P;
-    fp.P1a = P1;
-    fp.P1b = P1 ? P1 + leaf_floats : nullptr;
-    fp.B1a = B1;
-    fp.B1b = B1 + leaf_words;
-    fp.active = active;
     fp.unsat_last = unsat + (size_t)(max_iter & 1) * G;
-    fp.iters = iters;
-    fp.converged = conv;
-    fp.bits = bits;
-    fp.posterior = post;
-    fp.G = G;
     {
       ScopedTimer t(st, "k_finalize");
       hipLaunchKernelGGL(k_final_status<W>, dim3((B + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fp);
@@ -312,7 +489,7 @@ extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, u
 static int validate_decode(const met_code *c, int32_t B, uint32_t flags) {
   if (!c) return fail(MET_EINVAL, "NULL code");
   if (B < 1 || B > 65535) return fail(MET_EINVAL, "B = %d outside 1..65535", B);
-  if (flags & ~(uint32_t)MET_FIXED_ITERS) return fail(MET_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT)) return fail(MET_EINVAL, "unknown flags 0x%x", flags);
   return MET_OK;
 }
 

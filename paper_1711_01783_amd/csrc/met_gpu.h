@@ -474,8 +474,15 @@ struct VarParams {
   const uint64_t *unsat; // [G] test result of iteration it-1 (retire mode)
   int32_t *iters;
   uint8_t *converged;
+  const int32_t *slot_frame;  // [G*W] frame held by each lane, -1 none (NULL: lane s holds frame s)
   int32_t it, retire, G;
 };
+
+// Frame held by lane w of group g.
+template <int W>
+__device__ __forceinline__ int lane_frame(const int32_t *slot_frame, int g, int w) {
+  return slot_frame ? slot_frame[g * W + w] : g * W + w;
+}
 
 // Variable update: P_v = L_v + sum of c2v over v's message edges (gathered U
 // at a time, summed in list order).
@@ -493,7 +500,7 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
         if (done) {
           for (int w = 0; w < W; ++w)
             if ((done >> w) & 1ull) {
-              const int f = gg * W + w;
+              const int f = lane_frame<W>(p.slot_frame, gg, w);
               p.iters[f] = p.it - 1;
               p.converged[f] = 1;
             }
@@ -624,15 +631,18 @@ struct FinalParams {
   uint8_t *converged;
   uint8_t *bits;
   float *posterior;
+  const int32_t *slot_frame;  // as in VarParams
   int32_t G;
+  int32_t flush;  // k_finalize: write only frames that no longer run (lanes not in active)
 };
 
 // Outcome of frames still running after the last iteration.
 template <int W>
 __global__ void k_final_status(const FinalParams p) {
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < p.B; f += gridDim.x * blockDim.x) {
-    const int g = f / W, w = f % W;
-    if ((p.active[g] >> w) & 1ull) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < p.G * W; s += gridDim.x * blockDim.x) {
+    const int g = s / W, w = s % W;
+    const int f = lane_frame<W>(p.slot_frame, g, w);
+    if (f >= 0 && f < p.B && ((p.active[g] >> w) & 1ull)) {
       p.iters[f] = p.max_iter;
       p.converged[f] = (uint8_t)!((p.unsat_last[g] >> w) & 1ull);
     }
@@ -646,13 +656,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const FinalParams p) {
   __shared__ float val[64][W + 1];
   __shared__ uint8_t bit[64][W + 1];
   __shared__ uint8_t odd[W];
+  __shared__ int32_t frame[W];
   const int g = blockIdx.y;
   const int64_t v0 = (int64_t)blockIdx.x * 64;
+  bool any = false;
   if (threadIdx.x < W) {
-    const int f = g * W + threadIdx.x;
-    odd[threadIdx.x] = f < p.B ? (uint8_t)(p.iters[f] & 1) : 0;
+    int f = lane_frame<W>(p.slot_frame, g, threadIdx.x);
+    if (f >= p.B || (p.flush && ((p.active[g] >> threadIdx.x) & 1ull))) f = -1;
+    frame[threadIdx.x] = f;
+    odd[threadIdx.x] = f >= 0 ? (uint8_t)(p.iters[f] & 1) : 0;
+    any = f >= 0;
   }
-  __syncthreads();
+  if (!__syncthreads_or(any)) return;
   for (int idx = threadIdx.x; idx < W * 64; idx += kBlock) {
     const int v = idx / W, w = idx % W;
     float post = 0.0f;
@@ -674,8 +689,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const FinalParams p) {
   __syncthreads();
   for (int idx = threadIdx.x; idx < W * 64; idx += kBlock) {
     const int w = idx / 64, v = idx % 64;
-    const int f = g * W + w;
-    if (f >= p.B || v0 + v >= p.N) continue;
+    const int f = frame[w];
+    if (f < 0 || v0 + v >= p.N) continue;
     p.bits[(int64_t)f * p.N + v0 + v] = bit[v][w];
     if (p.posterior) p.posterior[(int64_t)f * p.N + v0 + v] = val[v][w];
   }
@@ -699,9 +714,14 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Plan {
   int W = 64, G = 1;
   size_t off_c2v = 0, off_P = 0, off_L2 = 0, off_Lphi = 0, off_Lraw = 0, off_P1 = 0, off_synw = 0, off_B1 = 0,
-         off_unsat = 0, off_active = 0, total = 0;
+         off_unsat = 0, off_active = 0, off_slot = 0, off_ctab = 0, total = 0;
   bool lraw = false, p1 = false;
 };
+
+// Compaction table (groups of 64 frames): the number of groups that receive
+// frames, their indices, and for each such group the lane each of its 64
+// lanes receives a frame from (source slot g * 64 + w, or -1).
+inline size_t compact_table_bytes(int G) { return 256 + align256((size_t)G * 4) + (size_t)G * 64 * 4; }
 
 // Frames per group: the smallest supported width that holds min(B, 64).
 int choose_interleave(int B) {
@@ -735,6 +755,8 @@ Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
   pl.off_B1 = take(2 * (size_t)pl.G * c->EL * sizeof(uint64_t));
   pl.off_unsat = take(2 * (size_t)pl.G * sizeof(uint64_t));
   pl.off_active = take((size_t)pl.G * sizeof(uint64_t));
+  pl.off_slot = take(GW * sizeof(int32_t));
+  pl.off_ctab = take(compact_table_bytes(pl.G));
   pl.total = o;
   return pl;
 }

@@ -114,3 +114,24 @@ def test_tree_codes_with_runtime_degree_checks():
     out = met.decode_batched(jobs)
     torch.cuda.synchronize()
     _same(out, _plain(jobs), "trees")
+
+
+def test_autotuner_picks_a_valid_shape_and_caches_it(mix):
+    import time
+
+    jobs = [j for j, _ in mix[:3]]
+    dec = met.BatchedDecoder()
+    t0 = time.perf_counter()
+    shape = dec.autotune(jobs, probe_iters=3)
+    t1 = time.perf_counter()
+    print("autotuned", shape, "in %.2f s" % (t1 - t0), flush=True)
+    assert shape["check_steps_per_wave"] in (1, 2, 4)
+    assert 1 <= shape["blocks_per_cu"] <= 6
+    assert shape["probe_ms"] > 0
+    again = met.BatchedDecoder().autotune(jobs, probe_iters=3)
+    assert again == shape                     # served from the cache
+    assert time.perf_counter() - t1 < 0.5 * (t1 - t0) + 0.05
+    out = dec(jobs)
+    torch.cuda.synchronize()
+    assert not dec.barrier_expired()
+    _same(out, _plain(jobs), "autotuned")

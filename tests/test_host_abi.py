@@ -189,3 +189,23 @@ def test_batched_argument_validation_without_gpu():
     t.batch_flags = 4
     assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
     assert L.met_batched_check(None, None) == -1
+
+
+def test_batched_autotune_validation_without_gpu():
+    c = met.Code.build(PROFILES["r0.1"], 4096, 1)
+    L = _lib.lib
+    jobs = (_lib.met_job * 1)()
+    jobs[0].code = c.handle
+    jobs[0].llr = jobs[0].syn = jobs[0].bits = jobs[0].iters = jobs[0].converged = 256
+    jobs[0].B = 64
+    jobs[0].max_iter = 20
+    n = ctypes.c_size_t()
+    assert L.met_batched_workspace_bytes(jobs, 1, ctypes.byref(n)) == 0
+    best = _lib.met_tuning()
+    ms = ctypes.c_float()
+    P = ctypes.c_void_p
+    assert L.met_batched_autotune(jobs, 1, P(256), n.value, 0, None, ctypes.byref(ms), None) == -1
+    assert L.met_batched_autotune(jobs, 1, P(256), n.value, -1, ctypes.byref(best), None, None) == -1
+    assert L.met_batched_autotune(jobs, 1, P(264), n.value, 0, ctypes.byref(best), None, None) == -1
+    assert L.met_batched_autotune(jobs, 1, P(256), n.value - 1, 0, ctypes.byref(best), None, None) == -1
+    assert L.met_batched_autotune(jobs, 0, P(256), n.value, 0, ctypes.byref(best), None, None) == -1
