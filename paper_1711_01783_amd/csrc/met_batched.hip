@@ -38,9 +38,13 @@ struct BatchJob {
 // barrier's group counters and the per-phase tile counters.  Every counter
 // sits on its own 128-byte line.
 struct BarrierState {
-  uint32_t count, gen;
-  int32_t err, pad;
+  uint32_t count;  // top-level arrivals (read-modify-written by group leaders)
+  uint32_t pad0[31];
+  uint32_t gen;    // generation, polled by every block (its own line)
+  int32_t err;     // set when a wait expired
+  uint32_t pad1[30];
 };
+static_assert(sizeof(BarrierState) == 256, "barrier state fills the first 256 bytes");
 
 constexpr int kLine = 32;                     // uint32 words per 128-byte line
 constexpr int kXcds = 8;                      // blocks are placed on XCD (block id mod 8)
@@ -52,7 +56,7 @@ constexpr size_t kOffTiles = kOffGroups + (size_t)kMaxBarrierGroups * kLine * 4;
 constexpr size_t kControlBytes = kOffTiles + (size_t)kCounterSets * kMaxJobs * kXcds * kLine * 4;
 constexpr int kMaxGrid = 32 * kXcds * (kMaxBarrierGroups / kXcds);  // 2048 blocks
 
-constexpr uint32_t kSpinLimit = 1u << 22;  // polls of about 0.1 us each
+constexpr uint32_t kSpinLimit = 1u << 21;  // polls of about 1 us each (load + sleep)
 
 __device__ __forceinline__ uint32_t *group_counter(char *ctl, int g) {
   return reinterpret_cast<uint32_t *>(ctl + kOffGroups) + (size_t)g * kLine;
@@ -97,13 +101,15 @@ __device__ int grid_barrier(char *ctl, uint32_t nblocks) {
       __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
+      // polls are spaced out so that the waiting blocks do not crowd the
+      // memory path of the blocks still working
       while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
-        if (__hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-        if (++spins == kSpinLimit) {
+        if ((++spins & 63) == 0 && __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        if (spins == kSpinLimit) {
           __hip_atomic_store(&b->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(10);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -178,21 +184,21 @@ __device__ __forceinline__ int64_t job_tiles(CJob *jobs, int j, int phase, int *
 }
 
 // Next job (from *cur, round-robin) that has tiles this phase and is not yet
-// exhausted on this XCD; its tile range on this XCD is [lo, hi).  Tiles of a
-// job's phase are split into one contiguous range per XCD.
+// exhausted on this XCD; *cnt = its number of tiles on this XCD.  XCD x takes
+// the tiles x, x + 8, x + 16, ... of a job's phase (as the hardware would
+// deal out blocks), so every XCD gets the same mix of check classes.
 __device__ bool next_range(CJob *jobs, int n_jobs, int phase, int xcd, int *cur, uint64_t *done, int *j,
-                           int64_t *lo, int64_t *hi) {
+                           int64_t *cnt) {
   for (int k = 0; k < n_jobs; ++k) {
     int jj = *cur + k;
     if (jj >= n_jobs) jj -= n_jobs;
     if ((*done >> jj) & 1ull) continue;
     int l = 0, kind = 0;
     const int64_t n = job_tiles(jobs, jj, phase, &l, &kind);
-    const int64_t a = n * xcd / kXcds, b = n * (xcd + 1) / kXcds;
-    if (b > a) {
+    const int64_t c = n > xcd ? (n - xcd + kXcds - 1) / kXcds : 0;
+    if (c > 0) {
       *j = jj;
-      *lo = a;
-      *hi = b;
+      *cnt = c;
       *cur = jj + 1 == n_jobs ? 0 : jj + 1;
       return true;
     }
@@ -217,10 +223,10 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) {
 // Claims the next tile for the block (wave 0 of the block, wave-uniformly):
 // -1 when every job's range on this XCD is exhausted for the phase.
 __device__ int64_t claim(CJob *jobs, int n_jobs, int phase, int xcd, char *ctl, int *cur, uint64_t *done, int *j) {
-  int64_t lo = 0, hi = 0;
-  while (next_range(jobs, n_jobs, phase, xcd, cur, done, j, &lo, &hi)) {
+  int64_t cnt = 0;
+  while (next_range(jobs, n_jobs, phase, xcd, cur, done, j, &cnt)) {
     const uint32_t v = wave_fetch_inc(tile_counter(ctl, phase % kCounterSets, *j, xcd));
-    if (lo + (int64_t)v < hi) return lo + v;
+    if ((int64_t)v < cnt) return xcd + (int64_t)v * kXcds;
     *done |= 1ull << *j;
   }
   return -1;
@@ -265,9 +271,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
       if (j < 0) break;
       const int64_t t = uniform64(s_tile[k]);
       int pj = -1;
-      int64_t plo = 0, phi = 0;
+      int64_t pcnt = 0;
       uint32_t pv = 0;
-      if (leader && next_range(jobs, n_jobs, phase, xcd, &cur, &done, &pj, &plo, &phi))
+      if (leader && next_range(jobs, n_jobs, phase, xcd, &cur, &done, &pj, &pcnt))
         pv = wave_fetch_inc(tile_counter(ctl, phase % kCounterSets, pj, xcd));
       int l = 0, kind = 0;
       (void)job_tiles(jobs, j, phase, &l, &kind);
@@ -278,8 +284,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
       if (leader) {
         int64_t nt = -1;
         if (pj >= 0) {
-          if (plo + (int64_t)pv < phi) {
-            nt = plo + pv;
+          if ((int64_t)pv < pcnt) {
+            nt = xcd + (int64_t)pv * kXcds;
           } else {
             done |= 1ull << pj;
             nt = claim(jobs, n_jobs, phase, xcd, ctl, &cur, &done, &pj);
