@@ -456,6 +456,14 @@ def run_wbp_train(args) -> dict:
     w = torch.ones(T, L, device="cuda:0", requires_grad=True)
     opt = torch.optim.Adam([w], lr=args.lr)
     losses = []
+    held = _wbp_setup(prof, n, B, snr, FRAME_SEED + 99991)  # not trained on
+
+    def held_loss():
+        with torch.no_grad():
+            post, _, _, _ = wbp.forward(held[0], held[1], held[2], w.detach().contiguous(), k)
+            return float(torch.nn.functional.softplus(-held[3] * post).mean())
+
+    loss_before = held_loss()
 
     def step(r=[0]):
         _, llr, syn, sgn = batches[r[0] % len(batches)]
@@ -482,7 +490,9 @@ def run_wbp_train(args) -> dict:
                                "iterations, checkpoint every %d, SNR %g, Adam lr %g, scales initialised to 1"
                                % (PROFILES[prof].rate, n, B, L, k, snr, args.lr),
                    "profile": prof, "N": n, "frames": B, "iterations": L, "ckpt_every": k, "snr": snr},
-        "loss_first": round(hist[0], 6), "loss_last": round(hist[-1], 6),
+        "heldout_loss_before": round(loss_before, 6), "heldout_loss_after": round(held_loss(), 6),
+        "train_loss_first_rotation": round(sum(hist[:4]) / 4, 6), "train_loss_last_rotation": round(sum(hist[-4:]) / 4, 6),
+        "training_steps": len(hist),
         "workspace_bytes": wbp.workspace_bytes(code, B, L, k),
     }
 
@@ -576,7 +586,7 @@ def main() -> int:
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")
     ap.add_argument("--no-autotune", action="store_true", help="mix: keep the default persistent launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=20, help="iterations per frame in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=80, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (scale for rocprofv3 byte counters)")
