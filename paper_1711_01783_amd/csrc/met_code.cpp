@@ -122,11 +122,42 @@ int finalize_code(met_code *c) {
   c->chk_msg_ptr.assign(M + 1, 0);
   c->chk_leaf_ptr.assign(M + 1, 0);
   c->max_check_deg = 0;
+  // Decoder order of the checks: within each run of checks of one shape
+  // (message and leaf edge counts), checks sorted by their smallest, then
+  // largest, message VN, so that checks sharing a VN are processed together
+  // and its posterior row is gathered once from HBM for several of them.
+  // Only the order of independent check updates changes.
+  std::vector<int32_t> nmsg(M), key_lo(M), key_hi(M);
   for (int64_t j = 0; j < M; ++j) {
     const int32_t d = c->chk_ptr[j + 1] - c->chk_ptr[j];
     if (d < 2 || d > MET_MAX_CHECK_DEGREE)
       return fail(MET_EINVAL, "check %lld has degree %d (allowed 2..%d)", (long long)j, d,
                   MET_MAX_CHECK_DEGREE);
+    int32_t nm = 0, lo = INT32_MAX, hi = -1;
+    for (int32_t e = c->chk_ptr[j]; e < c->chk_ptr[j + 1]; ++e)
+      if (deg[c->vn[e]] != 1) {
+        ++nm;
+        lo = std::min(lo, msg_index[c->vn[e]]);
+        hi = std::max(hi, msg_index[c->vn[e]]);
+      }
+    nmsg[j] = nm;
+    key_lo[j] = lo;
+    key_hi[j] = hi;
+  }
+  c->chk_orig.resize(M);
+  for (int64_t j = 0; j < M; ++j) c->chk_orig[j] = (int32_t)j;
+  for (int64_t a = 0; a < M;) {
+    const int32_t nm = nmsg[a], nl = (c->chk_ptr[a + 1] - c->chk_ptr[a]) - nm;
+    int64_t b = a + 1;
+    while (b < M && nmsg[b] == nm && (c->chk_ptr[b + 1] - c->chk_ptr[b]) - nmsg[b] == nl) ++b;
+    std::stable_sort(c->chk_orig.begin() + a, c->chk_orig.begin() + b, [&](int32_t x, int32_t y) {
+      return key_lo[x] != key_lo[y] ? key_lo[x] < key_lo[y] : key_hi[x] < key_hi[y];
+    });
+    a = b;
+  }
+  for (int64_t jj = 0; jj < M; ++jj) {
+    const int64_t j = c->chk_orig[jj];
+    const int32_t d = c->chk_ptr[j + 1] - c->chk_ptr[j];
     c->max_check_deg = std::max(c->max_check_deg, d);
     for (int32_t e = c->chk_ptr[j]; e < c->chk_ptr[j + 1]; ++e) {
       const int32_t v = c->vn[e];
@@ -139,8 +170,8 @@ int finalize_code(met_code *c) {
         c->edge_type_msg.push_back(c->et[e]);
       }
     }
-    c->chk_msg_ptr[j + 1] = (int32_t)c->edge_msgvn.size();
-    c->chk_leaf_ptr[j + 1] = (int32_t)c->leaf_vn_user.size();
+    c->chk_msg_ptr[jj + 1] = (int32_t)c->edge_msgvn.size();
+    c->chk_leaf_ptr[jj + 1] = (int32_t)c->leaf_vn_user.size();
   }
   for (int64_t i = 0; i < c->N2; ++i) c->vn_slot[c->msg_vn_user[i]] = (int32_t)i;
   c->E12 = (int64_t)c->edge_msgvn.size();

@@ -550,6 +550,7 @@ struct InitParams {
   const float *llr;       // [B][N]
   const uint8_t *syn;     // [B][M]
   const int32_t *msg_vn_user, *leaf_vn;
+  const int32_t *chk_orig;  // [M] decoder check order -> check of the code (syndrome index)
   int64_t N, M, N2, EL;
   int32_t B, G;
   float *Lt;              // [G][N][W] staging
@@ -600,10 +601,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_syndrome(const InitParams p) {
   const int g = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j < p.M) {
+    const int64_t jo = p.chk_orig[j];  // the syndrome is given in the code's check order
     uint64_t word = 0;
     for (int w = 0; w < W; ++w) {
       const int f = g * W + w;
-      if (f < p.B) word |= (uint64_t)(p.syn[(int64_t)f * p.M + j] & 1u) << w;
+      if (f < p.B) word |= (uint64_t)(p.syn[(int64_t)f * p.M + jo] & 1u) << w;
     }
     p.synw[(int64_t)g * p.M + j] = word;
   }

@@ -51,6 +51,7 @@ struct DeviceCode {
   const int32_t *chk_leaf_ptr = nullptr; // [M+1]
   const int32_t *all_vn = nullptr;       // [E] user VN of every edge (check order)
   const int32_t *all_ptr = nullptr;      // [M+1]
+  const int32_t *chk_orig = nullptr;     // [M] decoder check order -> check index of the code
 };
 
 }  // namespace met
@@ -65,7 +66,8 @@ struct met_code {
   // Derived decoder structures.
   int64_t N2 = 0, E12 = 0, EL = 0;
   std::vector<int32_t> msg_vn_user, edge_msgvn, vn_ptr, vn_edges, leaf_vn_user, vn_slot;
-  std::vector<int32_t> chk_msg_ptr, chk_leaf_ptr;
+  std::vector<int32_t> chk_msg_ptr, chk_leaf_ptr;  // [M+1] in decoder check order
+  std::vector<int32_t> chk_orig;                   // [M] decoder check -> check of the code
   std::vector<int8_t> edge_type_msg, leaf_type;
   std::vector<met::CheckClass> classes;
   int32_t max_check_deg = 0, max_vn_deg = 0;
