@@ -586,7 +586,7 @@ def main() -> int:
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")
     ap.add_argument("--no-autotune", action="store_true", help="mix: keep the default persistent launch shape")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=80, help="iterations per frame in the CPU sample")
+    ap.add_argument("--cpu-iters", type=int, default=50, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (scale for rocprofv3 byte counters)")
