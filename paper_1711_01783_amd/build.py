@@ -30,38 +30,49 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def command(out: str) -> list:
-    return [
-        hipcc(),
-        "--offload-arch=" + ARCH,
-        "-O3",
-        "-std=c++17",
-        "-fPIC",
-        "-shared",
-        "-Wall",
-        "-Wno-unused-function",
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-I", os.path.join(ROOT, "include"),
-        "-I", CSRC,
-        *[os.path.join(CSRC, s) for s in SOURCES],
-        "-o", out,
-    ]
+FLAGS = [
+    "--offload-arch=" + ARCH,
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-Wall",
+    "-Wno-unused-function",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = command(tmp)
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
-        if os.path.exists(tmp):
-            os.remove(tmp)
         raise RuntimeError("hipcc failed:\n" + err)
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles every source to an object in parallel, then links the library
+    (written to a temporary name and moved into place)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    tag = "%d" % os.getpid()
+    objs = [os.path.join(CSRC, s + ".%s.o" % tag) for s in SOURCES]
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    tmp = LIB + ".tmp" + tag
+    try:
+        with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+            jobs = [pool.submit(_run, [hipcc(), *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o], verbose)
+                    for s, o in zip(SOURCES, objs)]
+            for j in jobs:
+                j.result()
+        _run([hipcc(), *FLAGS, "-shared", *objs, "-o", tmp], verbose)
+        os.replace(tmp, LIB)
+    finally:
+        for f in objs + [tmp]:
+            if os.path.exists(f):
+                os.remove(f)
     return LIB
 
 
