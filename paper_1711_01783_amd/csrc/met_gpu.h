@@ -274,17 +274,23 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     }
     if (test) bad |= parity & (uint32_t)(valid[k] && lane_act);
     const uint32_t tot = (__popc(neg) & 1u) ^ s;
-    float pre[D], suf[D];
-    pre[0] = 0.0f;
+    // leave-one-out sums S[m] = sum of A over the other inputs, from prefix
+    // and suffix sums (no subtraction; no additions of zero)
+    float pre[D], suf[D], S[D];
+    pre[1] = A[0];
 #pragma unroll
-    for (int m = 1; m < D; ++m) pre[m] = pre[m - 1] + A[m - 1];
-    suf[D - 1] = 0.0f;
+    for (int m = 2; m < D; ++m) pre[m] = pre[m - 1] + A[m - 1];
+    suf[D - 2] = A[D - 1];
 #pragma unroll
-    for (int m = D - 2; m >= 0; --m) suf[m] = suf[m + 1] + A[m + 1];
+    for (int m = D - 3; m >= 0; --m) suf[m] = suf[m + 1] + A[m + 1];
+    S[0] = suf[0];
+    S[D - 1] = pre[D - 1];
+#pragma unroll
+    for (int m = 1; m < D - 1; ++m) S[m] = pre[m] + suf[m];
     const bool store = valid[k] && lane_act;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-      const float mag = phi(pre[m] + suf[m]);
+      const float mag = phi(S[m]);
       float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
       if (weighted) out *= ldro(p.weights, (int64_t)ldro(p.edge_type, m0 + m) * p.wstride + (p.it - 1));
       if (store) p.c2v[((int64_t)g * p.E12 + m0 + m) * W + w] = out;
@@ -292,22 +298,21 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const int64_t le = l0 + l;
-      const float S = pre[NM + l] + suf[NM + l];
       const uint32_t neg_l = (neg >> (NM + l)) & 1u;
       const uint32_t neg_c = (tot ^ neg_l) & 1u;
       float wt = 1.0f;
       if (weighted) wt = ldro(p.weights, (int64_t)ldro(p.leaf_type, le) * p.wstride + (p.it - 1));
       uint32_t bit;
       if (wt == 1.0f) {
-        bit = leaf_bit(neg_l, neg_c, S, A[NM + l]);
+        bit = leaf_bit(neg_l, neg_c, S[NM + l], A[NM + l]);
       } else {
         const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
-        const float mag = phi(S);
+        const float mag = phi(S[NM + l]);
         bit = (uint32_t)(lr + wt * (neg_c ? -mag : mag) < 0.0f);
       }
       if (post && store) {
         const float lr = p.Lraw[((int64_t)g * p.EL + le) * W + w];
-        const float mag = phi(S);
+        const float mag = phi(S[NM + l]);
         p.P1[((int64_t)g * p.EL + le) * W + w] = lr + wt * (neg_c ? -mag : mag);
       }
       const uint64_t ball = __ballot((int)(bit & (uint32_t)valid[k]));
