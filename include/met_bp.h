@@ -121,7 +121,11 @@ int met_code_info(const met_code *c, met_code_stats *out);
 /* A run of consecutive checks that one check kernel handles: n_msg edges to
  * variable nodes of degree >= 2 and n_leaf edges to degree-1 variable nodes per
  * check (-1 for runs of mixed shapes), and the number of distinct variable
- * nodes of degree >= 2 those checks reach. */
+ * nodes of degree >= 2 those checks reach.  first_check counts in the
+ * decoder's check order: the code's order with the checks of each such run
+ * sorted by their smallest (then largest) variable node of degree >= 2, so
+ * that checks sharing a node are updated together.  Syndromes and all other
+ * arguments stay in the code's own check order. */
 typedef struct {
   int32_t n_msg, n_leaf;
   int64_t first_check, n_checks;
