@@ -803,13 +803,13 @@ void launch_fixed_ipw(int ipw, int shape, unsigned blocks, int G, hipStream_t st
 template <int W>
 void launch_check(const CheckParams &p, const ClassArgs &a, int mode, int cn_ipw, int G, hipStream_t st) {
   const bool gen = a.shape == kShapeGeneric;
-  const int ipw = (W == 64 && !gen && mode != M_SPECIAL) ? cn_ipw : 1;
+  const int ipw = (W == 64 && !gen) ? cn_ipw : 1;
   const int64_t per_block = (int64_t)kWavesPerBlock * ipw * (64 / W);
   const unsigned blocks = (unsigned)((a.n_checks + per_block - 1) / per_block);
   if (gen)
     hipLaunchKernelGGL(k_check_generic<W>, dim3(blocks, G), dim3(kBlock), 0, st, p, a);
   else if (mode == M_SPECIAL)
-    launch_fixed<W, M_SPECIAL, 1>(a.shape, blocks, G, st, p, a);
+    launch_fixed_ipw<W, M_SPECIAL>(ipw, a.shape, blocks, G, st, p, a);
   else if (mode == M_FIRST)
     launch_fixed_ipw<W, M_FIRST>(ipw, a.shape, blocks, G, st, p, a);
   else

@@ -21,7 +21,9 @@
 //   xbar_e' = sgn(x_e') sum_{e != e'} Rbar_e sgn(R_e) sinh(A_e') / sinh(A_e' + r_ee')
 //       (A = phi(|x|), r_ee' = sum of A over the check's other inputs: the
 //        derivative of the leave-one-out boxplus, since phi'(y) = -1/sinh(y) and
-//        sinh(phi(y)) = 1/sinh(y))
+//        sinh(phi(y)) = 1/sinh(y)); evaluated without overflow or cancellation
+//        as e^{-r} expm1(-2 A_e') / expm1(-2 (A_e' + r_ee')), where
+//        A_e' + r_ee' is the leave-one-out sum of e.
 //   vbar_e' = xbar_e' where the clamp is inactive, else 0
 //   Cbar^{l-1}_e' = -vbar_e',   Pbar^{l-1}_v = sum_{e in E(v)} vbar_e.
 // Each segment between checkpoints is recomputed forward before its reverse
@@ -32,11 +34,6 @@ namespace met {
 namespace {
 
 constexpr int kMaxT = MET_MAX_EDGE_TYPES;
-
-// sinh(A) / sinh(A + r) for A > 0, r >= 0, without overflow or cancellation.
-__device__ __forceinline__ float sinh_ratio(float A, float r) {
-  return __expf(-r) * (expm1f(-2.0f * A) / expm1f(-2.0f * (A + r)));
-}
 
 struct AdjParams {
   const int32_t *edge_msgvn;
@@ -143,6 +140,13 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
     }
   }
   if (!p.first) {
+    // sinh(A_k) / sinh(S_e) = e^{-r_ek} expm1(-2 A_k) / expm1(-2 S_e), with
+    // S_e = A_k + r_ek the leave-one-out sum of e: the factor of e is shared
+    // by all targets k and the factor of k by all sources e.
+    float Qd[D];
+#pragma unroll UNR
+    for (int e = 0; e < D; ++e)
+      Qd[e] = e < nm + nl ? Q[e] * __builtin_amdgcn_rcpf(expm1f(-2.0f * (pre[e] + suf[e]))) : 0.0f;
 #pragma unroll UNR
     for (int k = 0; k < D; ++k) {
       if (k >= nm) continue;
@@ -154,10 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
       sb[D - 1] = 0.0f;
 #pragma unroll UNR
       for (int o = D - 2; o >= 0; --o) sb[o] = sb[o + 1] + (o + 1 == k ? 0.0f : A[o + 1]);
-      float xb = 0.0f;
+      float xs = 0.0f;
 #pragma unroll UNR
       for (int e = 0; e < D; ++e)
-        if (e != k && e < nm + nl) xb += Q[e] * sinh_ratio(A[k], pb[e] + sb[e]);
+        if (e != k && e < nm + nl) xs += Qd[e] * __expf(-(pb[e] + sb[e]));
+      float xb = expm1f(-2.0f * A[k]) * xs;
       if ((neg >> k) & 1u) xb = -xb;
       const float vbar = ((inrange >> k) & 1u) ? xb : 0.0f;
       if (valid) p.Cbar[((int64_t)g * p.E12 + m0 + k) * W + w] = -vbar;
@@ -198,6 +203,21 @@ __global__ __launch_bounds__(kBlock) void k_variable_adj(const VarAdjParams p) {
   for (int32_t e = ldro(p.vn_ptr, i); e < ldro(p.vn_ptr, i + 1); ++e) s += cb[(int64_t)ldro(p.vn_edges, e) * W];
   p.Pbar[((int64_t)g * p.N2 + i) * W + w] = -s;
 }
+
+// First level of the reduction of the per-block partial sums: block c sums
+// rows [c * chunk, (c + 1) * chunk) in a fixed order (the chunking depends only
+// on the row count, so the result is the same on every run).
+__global__ __launch_bounds__(kBlock) void k_reduce_wgrad_chunks(const float *partial, int64_t rows, int64_t chunk,
+                                                                float *out) {
+  const int t = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
+  float v = 0.0f;
+  for (int64_t r = r0 + lane; r < r1; r += 32) v += partial[r * kMaxT + t];
+  for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 32);
+  if (lane == 0) out[(int64_t)blockIdx.x * kMaxT + t] = v;
+}
+
+constexpr int kReduceChunks = 1024;
 
 // dLoss/dw[t][l] from the per-block partial sums (fixed summation order).
 __global__ __launch_bounds__(kBlock) void k_reduce_wgrad(const float *partial, int64_t rows, float *grad,
@@ -245,7 +265,8 @@ struct WbpPlan {
   int L = 0, k = 1, nck = 0, nseg = 0;
   size_t slot_c2v = 0, slot_P = 0, slot_bytes = 0;
   size_t off_slots = 0;  // work 1, checkpoints, segment states
-  size_t off_cbar = 0, off_pbar = 0, off_gleaf = 0, off_partial = 0, off_bits = 0, off_iters = 0, off_conv = 0;
+  size_t off_cbar = 0, off_pbar = 0, off_gleaf = 0, off_partial = 0, off_chunks = 0, off_bits = 0, off_iters = 0,
+         off_conv = 0;
   int64_t partial_rows = 0;
   size_t total = 0;
 };
@@ -281,6 +302,8 @@ WbpPlan make_wbp_plan(const met_code *c, int B, int L, int k) {
   p.partial_rows = adj_blocks(c, W) * p.base.G;
   p.off_partial = o;
   o += align256((size_t)p.partial_rows * kMaxT * sizeof(float));
+  p.off_chunks = o;
+  o += align256((size_t)kReduceChunks * kMaxT * sizeof(float));
   p.off_bits = o;
   o += align256((size_t)B * c->N);
   p.off_iters = o;
@@ -553,7 +576,17 @@ struct Wbp {
             row += (int64_t)blocks * G;
           }
         }
-        hipLaunchKernelGGL(k_reduce_wgrad, dim3(1), dim3(kBlock), 0, st, partial, row, grad_w, c->ntypes, pl.L, l);
+        {
+          // two levels: up to kReduceChunks blocks of fixed row ranges, then one block
+          ScopedTimer t(st, "k_reduce_wgrad");
+          const int64_t chunk = std::max<int64_t>(32, (row + kReduceChunks - 1) / kReduceChunks);
+          const int64_t nch = (row + chunk - 1) / chunk;
+          float *chunks = at<float>(pl.off_chunks);
+          if (nch > 0)
+            hipLaunchKernelGGL(k_reduce_wgrad_chunks, dim3((unsigned)nch), dim3(kBlock), 0, st, partial, row, chunk,
+                               chunks);
+          hipLaunchKernelGGL(k_reduce_wgrad, dim3(1), dim3(kBlock), 0, st, chunks, nch, grad_w, c->ntypes, pl.L, l);
+        }
         if (l > 1 && c->N2 > 0) {
           ScopedTimer t(st, "k_variable_adj");
           hipLaunchKernelGGL(k_variable_adj<W>, dim3((unsigned)((c->N2 + per - 1) / per), G), dim3(kBlock), 0, st,
