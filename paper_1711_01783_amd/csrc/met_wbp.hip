@@ -408,7 +408,7 @@ struct Wbp {
     const std::vector<ClassArgs> classes = class_args(c);
     for (const ClassArgs &a : classes) {
       ScopedTimer t(st, "k_check_weighted");
-      launch_check<W>(cp, a, M_SPECIAL, 1, b.G, st);
+      launch_check<W>(cp, a, M_SPECIAL, 4, b.G, st);
     }
     VarParams vp{};
     vp.vn_ptr = d->vn_ptr;
