@@ -155,6 +155,8 @@ int finalize_code(met_code *c) {
     });
     a = b;
   }
+  c->chk_pos.resize(M);
+  for (int64_t jj = 0; jj < M; ++jj) c->chk_pos[c->chk_orig[jj]] = (int32_t)jj;
   for (int64_t jj = 0; jj < M; ++jj) {
     const int64_t j = c->chk_orig[jj];
     const int32_t d = c->chk_ptr[j + 1] - c->chk_ptr[j];

@@ -216,7 +216,7 @@ struct Decoder {
     ip.syn = syn;
     ip.msg_vn_user = d->msg_vn_user;
     ip.leaf_vn = d->leaf_vn;
-    ip.chk_orig = d->chk_orig;
+    ip.chk_pos = d->chk_pos;
     ip.N = c->N;
     ip.M = c->M;
     ip.N2 = c->N2;
@@ -420,7 +420,7 @@ int device_code(const met_code *cc, const DeviceCode **out) {
       {c->msg_vn_user.data(), c->msg_vn_user.size() * 4, 0}, {c->vn_slot.data(), c->vn_slot.size() * 4, 0},
       {c->chk_msg_ptr.data(), c->chk_msg_ptr.size() * 4, 0}, {c->chk_leaf_ptr.data(), c->chk_leaf_ptr.size() * 4, 0},
       {c->vn.data(), c->vn.size() * 4, 0},                   {c->chk_ptr.data(), c->chk_ptr.size() * 4, 0},
-      {c->chk_orig.data(), c->chk_orig.size() * 4, 0},
+      {c->chk_pos.data(), c->chk_pos.size() * 4, 0},
   };
   size_t total = 0;
   for (Part &p : parts) {
@@ -453,7 +453,7 @@ int device_code(const met_code *cc, const DeviceCode **out) {
   d.chk_leaf_ptr = reinterpret_cast<const int32_t *>(b + parts[9].off);
   d.all_vn = reinterpret_cast<const int32_t *>(b + parts[10].off);
   d.all_ptr = reinterpret_cast<const int32_t *>(b + parts[11].off);
-  d.chk_orig = reinterpret_cast<const int32_t *>(b + parts[12].off);
+  d.chk_pos = reinterpret_cast<const int32_t *>(b + parts[12].off);
   d.ready = true;
   *out = &d;
   return MET_OK;

@@ -555,7 +555,7 @@ struct InitParams {
   const float *llr;       // [B][N]
   const uint8_t *syn;     // [B][M]
   const int32_t *msg_vn_user, *leaf_vn;
-  const int32_t *chk_orig;  // [M] decoder check order -> check of the code (syndrome index)
+  const int32_t *chk_pos;   // [M] check of the code (syndrome index) -> decoder check order
   int64_t N, M, N2, EL;
   int32_t B, G;
   float *Lt;              // [G][N][W] staging
@@ -606,13 +606,14 @@ __global__ __launch_bounds__(kBlock) void k_pack_syndrome(const InitParams p) {
   const int g = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j < p.M) {
-    const int64_t jo = p.chk_orig[j];  // the syndrome is given in the code's check order
+    // j counts in the code's check order (the syndrome's, so that the frame
+    // rows are read contiguously); the word goes to the decoder's position
     uint64_t word = 0;
     for (int w = 0; w < W; ++w) {
       const int f = g * W + w;
-      if (f < p.B) word |= (uint64_t)(p.syn[(int64_t)f * p.M + jo] & 1u) << w;
+      if (f < p.B) word |= (uint64_t)(p.syn[(int64_t)f * p.M + j] & 1u) << w;
     }
-    p.synw[(int64_t)g * p.M + j] = word;
+    p.synw[(int64_t)g * p.M + p.chk_pos[j]] = word;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int valid = min(W, p.B - g * W);

@@ -51,7 +51,7 @@ struct DeviceCode {
   const int32_t *chk_leaf_ptr = nullptr; // [M+1]
   const int32_t *all_vn = nullptr;       // [E] user VN of every edge (check order)
   const int32_t *all_ptr = nullptr;      // [M+1]
-  const int32_t *chk_orig = nullptr;     // [M] decoder check order -> check index of the code
+  const int32_t *chk_pos = nullptr;      // [M] check index of the code -> decoder check order
 };
 
 }  // namespace met
@@ -68,6 +68,7 @@ struct met_code {
   std::vector<int32_t> msg_vn_user, edge_msgvn, vn_ptr, vn_edges, leaf_vn_user, vn_slot;
   std::vector<int32_t> chk_msg_ptr, chk_leaf_ptr;  // [M+1] in decoder check order
   std::vector<int32_t> chk_orig;                   // [M] decoder check -> check of the code
+  std::vector<int32_t> chk_pos;                    // [M] check of the code -> decoder check
   std::vector<int8_t> edge_type_msg, leaf_type;
   std::vector<met::CheckClass> classes;
   int32_t max_check_deg = 0, max_vn_deg = 0;

@@ -349,7 +349,7 @@ struct Wbp {
     ip.syn = syn;
     ip.msg_vn_user = d->msg_vn_user;
     ip.leaf_vn = d->leaf_vn;
-    ip.chk_orig = d->chk_orig;
+    ip.chk_pos = d->chk_pos;
     ip.N = c->N;
     ip.M = c->M;
     ip.N2 = c->N2;
