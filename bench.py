@@ -439,6 +439,30 @@ def _wbp_setup(prof: str, n: int, B: int, snr: float, seed: int):
     return code, torch.from_numpy(llr).to("cuda:0"), syn, sgn
 
 
+def wbp_rooflines(code, frames: int, ktimes: dict) -> dict:
+    """Rooflines of the weighted check update and of the check adjoint from
+    per-launch timings.  Algorithmic bytes per frame: the weighted check update
+    moves what the plain one does (without the syndrome test) plus the leaf
+    LLRs (4 B per leaf edge, for the weighted leaf decision); the adjoint of a
+    class reads P and Pbar rows of the VNs it touches, c2v and Cbar and writes
+    Cbar (4 B each per message edge) and reads the leaf inputs."""
+    classes = [c for c in code.classes() if c["n_msg"] >= 0]
+    fwd = sum(class_bytes_per_frame(c, 64, first=False, test=False) + 4 * c["n_leaf"] * c["n_checks"]
+              for c in classes)
+    adj = sum(12 * c["n_msg"] * c["n_checks"] + 4 * c["n_leaf"] * c["n_checks"] + 8 * c["n_msg_vn_touched"]
+              for c in classes)
+    out = {}
+    lw, msw = ktimes.get("k_check_weighted", (0, 0.0))
+    if lw:
+        iters = lw / max(1, len(classes))
+        out["k_check_weighted"] = roofline("k_check_weighted (all classes of one iteration)", fwd * frames * iters,
+                                           int(iters), msw, None)
+    la, msa = ktimes.get("k_check_adj", (0, 0.0))
+    if la:
+        out["k_check_adj"] = roofline("k_check_adj (all classes of one iteration)", adj * frames * la, la, msa, None)
+    return out
+
+
 def run_wbp_train(args) -> dict:
     """Weighted-BP training steps: forward (L unrolled iterations, states kept
     every k-th), BCE loss, hand-written adjoint, Adam update of the [T, L]
@@ -480,6 +504,7 @@ def run_wbp_train(args) -> dict:
         step()
     torch.cuda.synchronize()
     ms = timed_plain(step, args.steps)
+    _, ktimes, _ = timed(step, 1, 0)  # per-launch timing for the rooflines
     hist = [float(x) for x in losses]
     return {
         "metric": "weighted-BP training: decoded Mbit/s (forward + adjoint + update per step)",
@@ -490,6 +515,7 @@ def run_wbp_train(args) -> dict:
                                "iterations, checkpoint every %d, SNR %g, Adam lr %g, scales initialised to 1"
                                % (PROFILES[prof].rate, n, B, L, k, snr, args.lr),
                    "profile": prof, "N": n, "frames": B, "iterations": L, "ckpt_every": k, "snr": snr},
+        "roofline": wbp_rooflines(code, B, ktimes),
         "heldout_loss_before": round(loss_before, 6), "heldout_loss_after": round(held_loss(), 6),
         "train_loss_first_rotation": round(sum(hist[:4]) / 4, 6), "train_loss_last_rotation": round(sum(hist[-4:]) / 4, 6),
         "training_steps": len(hist),
@@ -527,6 +553,7 @@ def run_wbp_eval(args) -> dict:
     for _ in range(args.warmup):
         step()
     ms = timed_plain(step, args.steps)
+    _, ktimes, _ = timed(step, 1, 0)  # per-launch timing for the rooflines
     # FER on fresh frames: trained scales vs plain BP, same syndromes, L iterations
     wt = w.detach().contiguous()
     errs_w = errs_p = conv_w = conv_p = 0
@@ -557,11 +584,12 @@ def run_wbp_eval(args) -> dict:
                                % (PROFILES[prof].rate, n, B, L, k, snr, L, total),
                    "profile": prof, "N": n, "frames": B, "iterations": L, "ckpt_every": k, "snr": snr},
         "workspace_bytes": wbp.workspace_bytes(code, B, L, k),
+        "roofline": wbp_rooflines(code, B, ktimes),
         "eval_frames": total,
         "fer_weighted": round(errs_w / total, 4), "fer_weighted_ci95": [round(x, 4) for x in wilson(errs_w, total)],
         "fer_plain": round(errs_p / total, 4), "fer_plain_ci95": [round(x, 4) for x in wilson(errs_p, total)],
         "converged_weighted": conv_w, "converged_plain": conv_p,
-        "training_steps": args.warmup + args.steps + 1,
+        "training_steps": args.warmup + args.steps + 2,
     }
 
 
