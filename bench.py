@@ -401,7 +401,7 @@ def run_single(args, cpu) -> dict:
 
     ms, kt, out = timed(step, args.steps, args.warmup)
     value = B * n * args.steps / (ms * 1e-3) / 1e6
-    W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 64
+    W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 32 if B <= 32 else 64
     early = not args.fixed_iters
     cls, var = job_bytes(code, out.iterations.cpu().numpy(), out.converged.cpu().numpy(), max_iter, early, W)
     classes = [c for c in code.classes() if c["n_msg"] >= 0]

@@ -539,6 +539,7 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
     case 1: return dec.run<1>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     case 4: return dec.run<4>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     case 16: return dec.run<16>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+    case 32: return dec.run<32>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     default: return dec.run<64>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   }
 }

@@ -736,6 +736,7 @@ int choose_interleave(int B) {
   if (B <= 1) return 1;
   if (B <= 4) return 4;
   if (B <= 16) return 16;
+  if (B <= 32) return 32;
   return 64;
 }
 

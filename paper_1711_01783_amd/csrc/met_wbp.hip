@@ -654,6 +654,7 @@ extern "C" int met_wbp_forward(const met_code *c, const float *llr, const uint8_
     case 1: return w.forward<1>(llr, syn, posterior, bits, converged);
     case 4: return w.forward<4>(llr, syn, posterior, bits, converged);
     case 16: return w.forward<16>(llr, syn, posterior, bits, converged);
+    case 32: return w.forward<32>(llr, syn, posterior, bits, converged);
     default: return w.forward<64>(llr, syn, posterior, bits, converged);
   }
 }
@@ -673,6 +674,7 @@ extern "C" int met_wbp_backward(const met_code *c, const float *grad_posterior, 
     case 1: return w.backward<1>(grad_posterior, grad_weights);
     case 4: return w.backward<4>(grad_posterior, grad_weights);
     case 16: return w.backward<16>(grad_posterior, grad_weights);
+    case 32: return w.backward<32>(grad_posterior, grad_weights);
     default: return w.backward<64>(grad_posterior, grad_weights);
   }
 }

@@ -61,6 +61,8 @@ POSTERIOR_CASES = [
     ("r0.02", 8192, 33, 0.068),
     ("r0.1", 4096, 1, 0.25),
     ("r0.02", 4096, 3, 0.0296),
+    ("r0.05", 8192, 32, 0.105),    # W = 32
+    ("r0.1", 4096, 20, 0.2),       # W = 32, ragged
 ]
 
 
@@ -171,7 +173,7 @@ def test_batch_invariance_and_determinism():
     again = _gpu_decode(code_g, llr, syn, 40, fixed=False)
     for x, y in zip(full, again):
         np.testing.assert_array_equal(x, y)
-    for lo, hi in ((0, 1), (5, 8), (64, 100), (30, 47)):
+    for lo, hi in ((0, 1), (5, 8), (64, 100), (30, 47), (2, 34), (40, 56)):
         sub = _gpu_decode(code_g, llr[lo:hi], syn[lo:hi], 40, fixed=False)
         for x, y in zip(full, sub):
             np.testing.assert_array_equal(x[lo:hi], y)
