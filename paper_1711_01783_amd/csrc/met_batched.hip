@@ -6,15 +6,15 @@
 // and variable update alternate phase by phase; jobs are staggered by one
 // phase, so the same phase holds check work of some jobs (ALU-heavy) and
 // variable work of others (memory-heavy) and the two kinds share the machine.
-// Every block walks the phase's tiles of all jobs round-robin (one tile of each
-// job in turn), so each compute unit runs a mix of both kinds.  A job whose
-// budget is spent stops contributing tiles; frames that converged are retired
-// exactly as in met_decode (the same device code runs here).
+// Blocks claim the phase's tiles dynamically, one job after the other, so each
+// compute unit runs a mix of both kinds.  A job whose budget is spent stops
+// contributing tiles; frames that converged are retired exactly as in
+// met_decode (the same device code runs here, so the results are identical).
 //
-// The grid is sized so that all blocks are resident at once (occupancy query),
-// which the barrier needs.  The barrier's wait is bounded: if it ever expires
-// (blocks not co-resident), an error flag is set and every block runs to its end
-// without waiting, so the launch always terminates; met_batched_check reports it.
+// The grid is sized so that all blocks are resident at once (occupancy query,
+// at most 6 blocks per compute unit), which the barrier needs.  The barrier's
+// wait is bounded: if it ever expires (blocks not co-resident), an error flag is
+// set, every block returns at its next barrier, and met_batched_check reports it.
 #include "met_gpu.h"
 
 namespace met {
