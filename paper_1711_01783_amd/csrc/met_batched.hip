@@ -591,7 +591,10 @@ struct Batched {
     append_bytes(k, gen);
     append_bytes(k, grid);
     append_bytes(k, n_phases);
-    for (int j = 0; j < n; ++j) append_bytes(k, jobs[j]);
+    for (int j = 0; j < n; ++j) {
+      append_bytes(k, jobs[j]);
+      append_bytes(k, jobs[j].code->uid);  // a new code at a freed code's address must not match
+    }
     return k;
   }
 
@@ -721,7 +724,7 @@ std::vector<uint8_t> tune_key(const met_job *jobs, int n, int probe_iters) {
   append_bytes(k, probe_iters);
   for (int j = 0; j < n; ++j) {
     const met_code *c = jobs[j].code;
-    append_bytes(k, c);
+    append_bytes(k, c->uid);
     append_bytes(k, c->N);
     append_bytes(k, c->M);
     append_bytes(k, c->E12);

@@ -23,6 +23,7 @@
 //      the check ends of i and j when j != i and neither new pair exists yet.
 //   8. Edges are sorted by (check, type, VN).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -238,6 +239,8 @@ int finalize_code(met_code *c) {
 
 using met::fail;
 
+static std::atomic<uint64_t> g_next_uid{0};
+
 extern "C" const char *met_last_error(void) { return met::g_last_error.c_str(); }
 
 static int sort_and_finalize(met_code *c, std::vector<int32_t> &v, std::vector<int32_t> &ch,
@@ -422,6 +425,7 @@ extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, me
     }
   }
   met_code *code = new (std::nothrow) met_code();
+  if (code) code->uid = g_next_uid.fetch_add(1) + 1;
   if (!code) return fail(MET_ENOMEM, "out of host memory");
   code->N = N;
   code->M = M;
@@ -469,6 +473,7 @@ extern "C" int met_code_from_edges(int64_t N, int64_t M, int64_t E, const int32_
       if (keys[e] == keys[e - 1]) return fail(MET_EINVAL, "repeated (VN, check) pair");
   }
   met_code *code = new (std::nothrow) met_code();
+  if (code) code->uid = g_next_uid.fetch_add(1) + 1;
   if (!code) return fail(MET_ENOMEM, "out of host memory");
   code->N = N;
   code->M = M;

@@ -57,6 +57,7 @@ struct DeviceCode {
 }  // namespace met
 
 struct met_code {
+  uint64_t uid = 0;  // unique per handle in this process (caches key on it, not on the address)
   int64_t N = 0, M = 0, E = 0;
   int32_t ntypes = 1;
   // Edge list in (check, type, VN) order.

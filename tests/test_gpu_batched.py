@@ -135,3 +135,26 @@ def test_autotuner_picks_a_valid_shape_and_caches_it(mix):
     torch.cuda.synchronize()
     assert not dec.barrier_expired()
     _same(out, _plain(jobs), "autotuned")
+
+
+def test_graph_cache_does_not_outlive_a_freed_code():
+    """Same buffers, sizes and host address for a new code after the old one was
+    freed: the cached graph of the old code must not be replayed."""
+    n, b = 4096, 64
+    d_llr = torch.empty((b, n), dtype=torch.float32, device=DEV)
+    outs = None
+    dec = met.BatchedDecoder()
+    syn_buf = None
+    for seed in (31, 32, 33):
+        code = met.Code.build(PROFILES["r0.1"], n, seed)
+        bits, llr = make_frames(n, b, 0.2, 900 + seed)
+        d_llr.copy_(torch.from_numpy(llr))
+        syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
+        if syn_buf is None:
+            syn_buf = syn.clone()
+        syn_buf.copy_(syn)
+        job = met.Job(code, d_llr, syn_buf, 12)
+        outs = dec([job], outputs=outs)
+        torch.cuda.synchronize()
+        _same(outs, _plain([job]), "seed %d" % seed)
+        code.close()
