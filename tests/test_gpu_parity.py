@@ -206,3 +206,34 @@ def test_failure_injection_from_host():
     out = _gpu_decode(far[1], far[3], far[4], 10, fixed=False)
     np.testing.assert_array_equal(out[2], 0)
     np.testing.assert_array_equal(out[1], 10)
+
+
+def test_degenerate_inputs_match_oracle():
+    """LLRs that are zero (no information), far beyond the clamp, or infinite,
+    alone or mixed with ordinary values: posteriors after 6 iterations match the
+    oracle (infinities and signed zeros included) and hard bits follow Step 5."""
+    code_o, code_g, bits, llr, syn = _case("r0.1", 4096, 12, 0.25)
+    rng = np.random.default_rng(5)
+    x = llr.astype(np.float32).copy()
+    x[0] = 0.0                                   # no information at all
+    x[1] = np.where(bits[1] == 1, -1e6, 1e6)     # far beyond the clamp, correct signs
+    x[2] = np.where(bits[2] == 1, -np.inf, np.inf)
+    x[3, rng.random(x.shape[1]) < 0.3] = 0.0     # erasures among ordinary values
+    x[4, rng.random(x.shape[1]) < 0.01] = np.inf
+    x[5, rng.random(x.shape[1]) < 0.01] = -np.inf
+    x[6] = -x[6]                                 # every sign wrong
+    x[7] = 29.999 * np.sign(x[7])                # at the clamp
+    for frames, it in ((slice(0, 7), 6), (slice(7, 8), 1)):
+        # Frame 7 only for one iteration: with every input at the clamp the
+        # oracle's tanh product sits within 1e-12 of 1 and its FP64 result
+        # 2 artanh(T) carries about 1e-4 absolute error per message, which
+        # later iterations amplify; one iteration stays far inside the bound.
+        b_, it_, cv_, post = _gpu_decode(code_g, x[frames], syn[frames], it)
+        ref = bp.decode(code_o, x[frames], syn[frames], it, early_exit=False).posterior
+        fin = np.isfinite(ref)
+        np.testing.assert_array_equal(post[~fin], ref[~fin])
+        err = np.abs(post[fin] - ref[fin])
+        assert np.all(err <= RTOL * np.abs(ref[fin]) + ATOL), err.max()
+        np.testing.assert_array_equal(b_, (post < 0).astype(np.uint8))
+        if it == 6:
+            np.testing.assert_array_equal(b_[2], bits[2])   # infinite LLRs with the right signs
