@@ -47,7 +47,6 @@ struct BarrierState {
 static_assert(sizeof(BarrierState) == 256, "barrier state fills the first 256 bytes");
 
 constexpr int kLine = 32;                     // uint32 words per 128-byte line
-constexpr int kXcds = 8;                      // blocks are placed on XCD (block id mod 8)
 constexpr int kMaxBarrierGroups = 64;         // groups of at most 32 blocks of one XCD
 constexpr int kMaxJobs = 64;
 constexpr int kCounterSets = 3;               // tile counters rotate over phases
@@ -185,8 +184,10 @@ __device__ __forceinline__ int64_t job_tiles(CJob *jobs, int j, int phase, int *
 
 // Next job (from *cur, round-robin) that has tiles this phase and is not yet
 // exhausted on this XCD; *cnt = its number of tiles on this XCD.  XCD x takes
-// the tiles x, x + 8, x + 16, ... of a job's phase (as the hardware would
-// deal out blocks), so every XCD gets the same mix of check classes.
+// the tiles x, x + 8, x + 16, ... of a job's phase (as the hardware deals out
+// blocks), so every XCD gets the same mix of check classes.  (Contiguous
+// ranges per XCD, faster in the plain kernels, were 3 % slower here, also
+// when split per check class.)
 __device__ bool next_range(CJob *jobs, int n_jobs, int phase, int xcd, int *cur, uint64_t *done, int *j,
                            int64_t *cnt) {
   for (int k = 0; k < n_jobs; ++k) {

@@ -61,6 +61,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr float kLlrMax = 30.0f;
+constexpr int kXcds = 8;  // accelerator dies; the hardware deals block b to die b mod 8
 
 enum : int32_t {
   F_FIRST = 1,     // iteration 1: P = L, c2v = 0
@@ -98,6 +99,28 @@ __device__ __forceinline__ float phi(float x) {
 // Index of the calling wave within its block, as a wave-uniform value (so that
 // per-wave addresses stay in scalar registers and index loads are scalar).
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Tile of block b of nb: each XCD takes one contiguous range of tiles, in
+// order (rather than every 8th tile), so neighbouring checks, which share
+// variable nodes in the decoder check order, and neighbouring variable nodes
+// meet in the same L2.  Contiguous ranges measured 3 % faster per iteration
+// than the hardware's round-robin order on the decoder kernels.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+  return x * q + min(x, r) + k;
+}
+
+// The same over a grid of (tiles, frame groups): the hardware deals blocks
+// by their linear index, so the ranges run over the linear tile index.
+struct GridTile {
+  int64_t bx;
+  int g;
+};
+__device__ __forceinline__ GridTile xcd_grid_tile() {
+  const int64_t nx = gridDim.x;
+  const int64_t t = xcd_tile((int64_t)blockIdx.y * nx + blockIdx.x, nx * gridDim.y);
+  return {t % nx, (int)(t / nx)};
+}
 
 // Load from memory that no kernel writes while the current one runs (the
 // adjacency, packed syndromes, decisions of the previous iteration).  Going
@@ -327,7 +350,8 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
 
 template <int W, int NM, int NL, int MODE, int IPW>
 __global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, const ClassArgs c) {
-  check_fixed_body<W, NM, NL, MODE, IPW, false>(p, c, blockIdx.x, blockIdx.y);
+  const GridTile t = xcd_grid_tile();
+  check_fixed_body<W, NM, NL, MODE, IPW, false>(p, c, t.bx, t.g);
 }
 
 // Check update with run-time degrees (total degree <= MET_MAX_CHECK_DEGREE),
@@ -436,7 +460,8 @@ __device__ __forceinline__ void check_generic_body(const CheckParams &p, const C
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, const ClassArgs c) {
-  check_generic_body<W, false>(p, c, blockIdx.x, blockIdx.y);
+  const GridTile t = xcd_grid_tile();
+  check_generic_body<W, false>(p, c, t.bx, t.g);
 }
 
 // Syndrome test only (after the last iteration): parity of the hard decisions
@@ -545,7 +570,8 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
 
 template <int W, int U>
 __global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
-  variable_body<W, U, false>(p, blockIdx.x, blockIdx.y);
+  const GridTile t = xcd_grid_tile();
+  variable_body<W, U, false>(p, t.bx, t.g);
 }
 
 // ----------------------------------------------------------------------------
