@@ -100,26 +100,30 @@ __device__ __forceinline__ float phi(float x) {
 // per-wave addresses stay in scalar registers and index loads are scalar).
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
-// Tile of block b of nb: each XCD takes one contiguous range of tiles, in
-// order (rather than every 8th tile), so neighbouring checks, which share
-// variable nodes in the decoder check order, and neighbouring variable nodes
-// meet in the same L2.  Contiguous ranges measured 3 % faster per iteration
-// than the hardware's round-robin order on the decoder kernels.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
-  const int64_t x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
-  return x * q + min(x, r) + k;
-}
-
-// The same over a grid of (tiles, frame groups): the hardware deals blocks
-// by their linear index, so the ranges run over the linear tile index.
+// Tile of block (bx, g) of a (tiles, frame groups) grid: within each frame
+// group, each XCD takes one contiguous range of tiles in order (rather than
+// every 8th tile), so neighbouring checks, which share variable nodes in the
+// decoder check order, and neighbouring variable nodes meet in the same L2.
+// The hardware deals blocks by their linear index, so block (bx, g) runs on
+// XCD (g nx + bx) mod 8; the XCDs' ranges are laid out in XCD order, and the
+// groups keep the dispatch order (one after the other on all XCDs).  Measured
+// against the hardware order: variable update 4 % and main check update 1 %
+// faster; the weighted check update and the adjoint kernels were 2-3 % slower
+// and keep the hardware order.
 struct GridTile {
   int64_t bx;
   int g;
 };
 __device__ __forceinline__ GridTile xcd_grid_tile() {
-  const int64_t nx = gridDim.x;
-  const int64_t t = xcd_tile((int64_t)blockIdx.y * nx + blockIdx.x, nx * gridDim.y);
-  return {t % nx, (int)(t / nx)};
+  const int64_t nx = gridDim.x, bx = blockIdx.x;
+  const int s = (int)(((int64_t)blockIdx.y * nx) % kXcds);  // XCD of the group's first block
+  const int x = (int)((s + bx) % kXcds);
+  int64_t first = 0;  // tiles of the XCDs before x
+  for (int y = 0; y < x; ++y) {
+    const int64_t r = (y - s + kXcds) % kXcds;  // first block of the group on XCD y
+    if (r < nx) first += (nx - r + kXcds - 1) / kXcds;
+  }
+  return {first + bx / kXcds, (int)blockIdx.y};
 }
 
 // Load from memory that no kernel writes while the current one runs (the
@@ -350,7 +354,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
 
 template <int W, int NM, int NL, int MODE, int IPW>
 __global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, const ClassArgs c) {
-  const GridTile t = xcd_grid_tile();
+  const GridTile t = MODE == M_SPECIAL ? GridTile{blockIdx.x, (int)blockIdx.y} : xcd_grid_tile();
   check_fixed_body<W, NM, NL, MODE, IPW, false>(p, c, t.bx, t.g);
 }
 

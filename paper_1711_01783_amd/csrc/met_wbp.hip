@@ -62,11 +62,10 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
   constexpr bool GEN = NM == 0;
   constexpr int D = GEN ? kMaxAdjDegree : NM + NL;
   constexpr int UNR = GEN ? 1 : D;  // compiled shapes unroll fully
-  const GridTile gt = xcd_grid_tile();
-  const int g = gt.g;
+  const int g = blockIdx.y;
   const int lane = threadIdx.x & 63, wv = wave_id();
   const int w = lane % W, q = lane / W;
-  const int64_t i = (gt.bx * kWavesPerBlock + wv) * (64 / W) + q;
+  const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wv) * (64 / W) + q;
   const bool valid = i < c.n_checks;
   const int64_t item = valid ? i : 0;
   const int64_t j = c.first_check + item;
@@ -195,10 +194,9 @@ struct VarAdjParams {
 
 template <int W>
 __global__ __launch_bounds__(kBlock) void k_variable_adj(const VarAdjParams p) {
-  const GridTile gt = xcd_grid_tile();
-  const int g = gt.g;
+  const int g = blockIdx.y;
   const int lane = threadIdx.x & 63, w = lane % W, q = lane / W;
-  const int64_t i = (gt.bx * kWavesPerBlock + wave_id()) * (64 / W) + q;
+  const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wave_id()) * (64 / W) + q;
   if (i >= p.N2) return;
   const float *cb = p.Cbar + (int64_t)g * p.E12 * W + w;
   float s = 0.0f;
