@@ -60,6 +60,15 @@ extern "C" {
                                a quarter of the occupied groups; results are
                                identical either way; no compaction when
                                posteriors are requested) */
+#define MET_NO_DEG1_SKIP 4u /* degree-1 variable nodes take part in every
+                               iteration like the others (their check messages
+                               are stored and their posteriors updated; the
+                               Table 1 "all VNs" reference); by default they
+                               never enter the iterations.  The results agree
+                               with the default to FP32 rounding: a degree-1
+                               node's message is re-formed as (L + c) - c
+                               instead of L.  The first such call builds a
+                               second layout of the code (host and device). */
 
 #define MET_MAX_EDGE_TYPES 8
 #define MET_MAX_CHECK_DEGREE 32
@@ -167,6 +176,7 @@ int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int
  *   syn:       dev uint8   [B][M]
  *   max_iter:  >= 1
  *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS, optionally | MET_NO_COMPACT
+ *              and/or | MET_NO_DEG1_SKIP
  *   bits:      dev uint8 [B][N] output, hard decisions at each frame's stop
  *   iters:     dev int32 [B] output, iterations run (1..max_iter)
  *   converged: dev uint8 [B] output, 1 iff H bits = syn

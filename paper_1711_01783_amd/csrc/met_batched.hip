@@ -157,6 +157,7 @@ __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) 
     case 3: check_fixed_body<kBatchW, 11, 0, M_MAIN, I2, true>(p, a, r, gi); break;
     case 4: check_fixed_body<kBatchW, 6, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
     case 5: check_fixed_body<kBatchW, 5, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 6: check_fixed_body<kBatchW, 4, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
     default:
       if (GEN) check_generic_body<kBatchW, true>(p, a, r, gi);
       break;

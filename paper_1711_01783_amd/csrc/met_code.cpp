@@ -94,10 +94,13 @@ struct PairCounts {
 
 // Derived structures for the decoder: message/leaf split, VN edge lists,
 // check classes.
-int finalize_code(met_code *c) {
+int finalize_code(met_code *c, bool skip_deg1) {
   const int64_t N = c->N, M = c->M, E = c->E;
   std::vector<int32_t> deg(N, 0);
   for (int64_t e = 0; e < E; ++e) deg[c->vn[e]]++;
+  // leaf edges: edges to degree-1 variable nodes, when those stay out of the
+  // iterations
+  auto is_leaf = [&](int32_t v) { return skip_deg1 && deg[v] == 1; };
   c->chk_ptr.assign(M + 1, 0);
   for (int64_t e = 0; e < E; ++e) c->chk_ptr[c->cn[e] + 1]++;
   for (int64_t j = 0; j < M; ++j) c->chk_ptr[j + 1] += c->chk_ptr[j];
@@ -108,9 +111,8 @@ int finalize_code(met_code *c) {
   std::vector<int32_t> msg_index(N, -1);
   for (int64_t v = 0; v < N; ++v) {
     c->max_vn_deg = std::max(c->max_vn_deg, deg[v]);
-    if (deg[v] == 1) {
-      c->n_deg1++;
-    } else {
+    if (deg[v] == 1) c->n_deg1++;
+    if (!is_leaf((int32_t)v)) {
       msg_index[v] = (int32_t)c->msg_vn_user.size();
       c->msg_vn_user.push_back((int32_t)v);
     }
@@ -136,7 +138,7 @@ int finalize_code(met_code *c) {
                   MET_MAX_CHECK_DEGREE);
     int32_t nm = 0, lo = INT32_MAX, hi = -1;
     for (int32_t e = c->chk_ptr[j]; e < c->chk_ptr[j + 1]; ++e)
-      if (deg[c->vn[e]] != 1) {
+      if (!is_leaf(c->vn[e])) {
         ++nm;
         lo = std::min(lo, msg_index[c->vn[e]]);
         hi = std::max(hi, msg_index[c->vn[e]]);
@@ -164,7 +166,7 @@ int finalize_code(met_code *c) {
     c->max_check_deg = std::max(c->max_check_deg, d);
     for (int32_t e = c->chk_ptr[j]; e < c->chk_ptr[j + 1]; ++e) {
       const int32_t v = c->vn[e];
-      if (deg[v] == 1) {
+      if (is_leaf(v)) {
         c->vn_slot[v] = -(int32_t)c->leaf_vn_user.size() - 1;
         c->leaf_vn_user.push_back(v);
         c->leaf_type.push_back(c->et[e]);
@@ -242,6 +244,31 @@ using met::fail;
 static std::atomic<uint64_t> g_next_uid{0};
 
 extern "C" const char *met_last_error(void) { return met::g_last_error.c_str(); }
+
+int met::all_vns_view(const met_code *cc, const met_code **out) {
+  met_code *c = const_cast<met_code *>(cc);
+  std::lock_guard<std::mutex> lock(c->mu);
+  if (!c->all_vns) {
+    met_code *v = new (std::nothrow) met_code;
+    if (!v) return fail(MET_ENOMEM, "out of host memory");
+    v->N = c->N;
+    v->M = c->M;
+    v->E = c->E;
+    v->ntypes = c->ntypes;
+    v->vn = c->vn;
+    v->cn = c->cn;
+    v->et = c->et;
+    const int rc = finalize_code(v, false);
+    if (rc) {
+      delete v;
+      return rc;
+    }
+    v->uid = ++g_next_uid;
+    c->all_vns = v;
+  }
+  *out = c->all_vns;
+  return MET_OK;
+}
 
 static int sort_and_finalize(met_code *c, std::vector<int32_t> &v, std::vector<int32_t> &ch,
                              std::vector<int8_t> &t) {

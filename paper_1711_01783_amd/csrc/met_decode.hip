@@ -465,6 +465,7 @@ using met::fail;
 
 extern "C" void met_code_free(met_code *c) {
   if (!c) return;
+  met_code_free(c->all_vns);
   int cur = -1;
   const bool have = hipGetDevice(&cur) == hipSuccess;
   for (int k = 0; k < met::kMaxDevices; ++k) {
@@ -492,7 +493,16 @@ extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, u
 static int validate_decode(const met_code *c, int32_t B, uint32_t flags) {
   if (!c) return fail(MET_EINVAL, "NULL code");
   if (B < 1 || B > 65535) return fail(MET_EINVAL, "B = %d outside 1..65535", B);
-  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT)) return fail(MET_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT | MET_NO_DEG1_SKIP))
+    return fail(MET_EINVAL, "unknown flags 0x%x", flags);
+  return MET_OK;
+}
+
+// The layout a decode with these flags runs on: the code's own, or its view
+// with degree-1 variable nodes iterated.
+static int decode_layout(const met_code *c, uint32_t flags, const met_code **out) {
+  if (flags & MET_NO_DEG1_SKIP) return met::all_vns_view(c, out);
+  *out = c;
   return MET_OK;
 }
 
@@ -502,6 +512,8 @@ extern "C" int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t
   int rc = validate_decode(c, B, flags);
   if (rc) return rc;
   if (!bytes) return fail(MET_EINVAL, "NULL bytes");
+  rc = decode_layout(c, flags, &c);
+  if (rc) return rc;
   *bytes = met::make_plan(c, B, want_posterior != 0, false, met::choose_interleave(B)).total;
   return MET_OK;
 }
@@ -528,6 +540,8 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
     for (int r = 0; r < 4; ++r)
       if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
   }
+  rc = decode_layout(c, flags, &c);
+  if (rc) return rc;
   const int W = met::choose_interleave(B);
   const met::Plan pl = met::make_plan(c, B, posterior != nullptr, false, W);
   if (ws_bytes < pl.total) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, pl.total);

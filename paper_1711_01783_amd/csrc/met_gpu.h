@@ -815,7 +815,8 @@ void launch_fixed(int shape, unsigned blocks, int G, hipStream_t st, const Check
     case 2: hipLaunchKernelGGL((k_check_fixed<W, 12, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
     case 3: hipLaunchKernelGGL((k_check_fixed<W, 11, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
     case 4: hipLaunchKernelGGL((k_check_fixed<W, 6, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
-    default: hipLaunchKernelGGL((k_check_fixed<W, 5, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+    case 5: hipLaunchKernelGGL((k_check_fixed<W, 5, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+    default: hipLaunchKernelGGL((k_check_fixed<W, 4, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
   }
 }
 
@@ -867,9 +868,10 @@ inline std::vector<ClassArgs> class_args(const met_code *c) {
 // Timer names of the check kernels, by shape.
 const char *const kCheckKernelName[kNumFixedShapes + 1] = {
     "k_check<3,1>", "k_check<2,1>", "k_check<12,0>", "k_check<11,0>", "k_check<6,0>", "k_check<5,0>",
-    "k_check_generic"};
-static_assert(kShapeMsg[0] == 3 && kShapeLeaf[0] == 1 && kShapeMsg[2] == 12 && kShapeMsg[5] == 5,
-              "timer names follow the shape table");
+    "k_check<4,0>", "k_check_generic"};
+static_assert(kShapeMsg[0] == 3 && kShapeLeaf[0] == 1 && kShapeMsg[2] == 12 && kShapeMsg[5] == 5 &&
+                  kShapeMsg[6] == 4 && kNumFixedShapes == 7,
+              "timer names and kernel switches follow the shape table");
 
 }  // namespace
 }  // namespace met

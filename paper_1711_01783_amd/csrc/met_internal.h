@@ -17,10 +17,11 @@ void clear_error();
 // Check shapes with a compiled kernel path: (message edges, leaf edges) per
 // check.  "Message" edges go to variable nodes of degree >= 2; "leaf" edges go
 // to degree-1 variable nodes, whose variable-to-check message is always the
-// channel LLR and which therefore never enter the iterations.
-constexpr int kNumFixedShapes = 6;
-constexpr int kShapeMsg[kNumFixedShapes] = {3, 2, 12, 11, 6, 5};
-constexpr int kShapeLeaf[kNumFixedShapes] = {1, 1, 0, 0, 0, 0};
+// channel LLR and which therefore never enter the iterations.  (4, 0) is the
+// 4-check of the MET profiles when degree-1 nodes are iterated like the others.
+constexpr int kNumFixedShapes = 7;
+constexpr int kShapeMsg[kNumFixedShapes] = {3, 2, 12, 11, 6, 5, 4};
+constexpr int kShapeLeaf[kNumFixedShapes] = {1, 1, 0, 0, 0, 0, 0};
 constexpr int kShapeGeneric = kNumFixedShapes;  // per-check row pointers
 
 constexpr int kMaxClasses = 16;
@@ -76,11 +77,19 @@ struct met_code {
   int64_t n_deg1 = 0;
   std::mutex mu;
   met::DeviceCode dev[met::kMaxDevices];
+  // The same graph with every variable node iterated, degree-1 nodes included
+  // (no leaf edges); built on first use by decodes with MET_NO_DEG1_SKIP.
+  met_code *all_vns = nullptr;
 };
 
 namespace met {
 // Builds the derived structures from (vn, cn, et); returns MET_OK or an error.
-int finalize_code(met_code *c);
+// With skip_deg1 false, degree-1 variable nodes are message nodes like the
+// others (no leaf edges).
+int finalize_code(met_code *c, bool skip_deg1 = true);
+// The code's view with every variable node iterated (c->all_vns), built on
+// first use.
+int all_vns_view(const met_code *c, const met_code **out);
 // Uploads the adjacency to the current device if needed (decoder side).
 int device_code(const met_code *c, const DeviceCode **out);
 }  // namespace met

@@ -495,6 +495,7 @@ struct Wbp {
       case 3: hipLaunchKernelGGL((k_check_adj<W, 11, 0>), grid, block, 0, st, p, a); break;
       case 4: hipLaunchKernelGGL((k_check_adj<W, 6, 0>), grid, block, 0, st, p, a); break;
       case 5: hipLaunchKernelGGL((k_check_adj<W, 5, 0>), grid, block, 0, st, p, a); break;
+      case 6: hipLaunchKernelGGL((k_check_adj<W, 4, 0>), grid, block, 0, st, p, a); break;
       default: hipLaunchKernelGGL((k_check_adj<W, 0, 0>), grid, block, 0, st, p, a); break;
     }
   }

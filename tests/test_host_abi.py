@@ -110,7 +110,7 @@ def test_decode_argument_validation_without_gpu():
     dummy = P(256)
     n = ctypes.c_size_t()
     assert L.met_decode_workspace_bytes(c.handle, 0, 0, 0, ctypes.byref(n)) == -1
-    assert L.met_decode_workspace_bytes(c.handle, 64, 7, 0, ctypes.byref(n)) == -1
+    assert L.met_decode_workspace_bytes(c.handle, 64, 8, 0, ctypes.byref(n)) == -1
     assert L.met_decode_workspace_bytes(None, 64, 0, 0, ctypes.byref(n)) == -1
     assert L.met_decode_workspace_bytes(c.handle, 64, 0, 0, ctypes.byref(n)) == 0 and n.value > 0
     big = n.value
@@ -128,8 +128,10 @@ def test_decode_argument_validation_without_gpu():
     assert call(llr=P(258)) == -1          # misaligned float buffer
     assert call(ws=P(264)) == -1           # workspace not 256-byte aligned
     assert call(wsb=big - 1) == -1         # too small
-    assert call(flags=4) == -1
-    assert "workspace" in L.met_last_error().decode() or "flags" in L.met_last_error().decode()
+    assert call(flags=8) == -1
+    assert "flags" in L.met_last_error().decode()
+    assert call(flags=4) == -1             # the all-VN layout needs a larger workspace
+    assert "workspace" in L.met_last_error().decode()
     assert L.met_syndrome(c.handle, None, 1, dummy, None) == -1
     assert L.met_syndrome(c.handle, dummy, 0, dummy, None) == -1
 
@@ -140,6 +142,21 @@ def test_workspace_grows_with_batch_and_posterior():
     b = met.workspace_bytes(c, 64)
     d = met.workspace_bytes(c, 64, posterior=True)
     assert a < b < d
+
+
+def test_all_vn_layout_sizes():
+    """MET_NO_DEG1_SKIP decodes on a layout where degree-1 variable nodes are
+    message nodes: every edge is a message edge and every node has a
+    posterior row, so its workspace is larger; the code itself is unchanged."""
+    c = met.Code.build(PROFILES["r0.1"], 8192, 3)
+    info = c.info()
+    a = met.workspace_bytes(c, 64)
+    b = met.workspace_bytes(c, 64, deg1_skip=False)
+    assert b > a
+    assert met.workspace_bytes(c, 64, deg1_skip=False) == b  # the view is built once and kept
+    assert c.info() == info
+    # the extra bytes are at least the degree-1 nodes' check messages and rows
+    assert b - a >= 64 * 4 * info["n_deg1"]
 
 
 def test_free_is_idempotent():
