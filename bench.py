@@ -40,7 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from met_inputs import BJ_SNR, ITER_BUDGET, PROFILES, make_frames  # noqa: E402
+from met_inputs import BJ_SNR, ITER_BUDGET, PROFILES, WATERFALL_SNR, make_frames  # noqa: E402
 
 METRIC = "decoded Mbit/s at N=1e6, R=0.1/0.05/0.02 (batched vs plain, equal FER); % HBM peak"
 HBM_PEAK_GBS = 8000.0
@@ -277,6 +277,56 @@ def fer_summary(out, bits):
             "undetected_errors": int((err & (conv == 1)).sum()), "mean_iterations": round(float(iters.mean()), 2)}
 
 
+def job_snr(args, prof: str) -> float:
+    """The SNR of a job: --snr if given, else the waterfall point (--waterfall)
+    or the workload's operating point."""
+    if args.snr is not None:
+        return args.snr
+    return WATERFALL_SNR[prof] if args.waterfall else BJ_SNR[prof]
+
+
+def copy_bandwidth() -> float:
+    """Measured device-to-device copy rate in GB/s (bytes read + written)."""
+    import torch
+
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = timed_plain(lambda: b.copy_(a), 5)
+    del a, b
+    return 2 * 4 * n * 5 / (ms * 1e-3) / 1e9
+
+
+def end_to_end(jobs, dec, steps: int) -> dict:
+    """One batched step with the inputs in pinned host memory: host-to-device
+    copies of LLRs and syndromes, the decode, device-to-host copies of bits,
+    iteration counts and flags (the paper's timing includes its copies)."""
+    import torch
+
+    h_in = [(j.llr.cpu().pin_memory(), j.syn.cpu().pin_memory()) for j in jobs]
+    h_out = [(torch.empty(tuple(j.llr.shape), dtype=torch.uint8).pin_memory(),
+              torch.empty(int(j.llr.shape[0]), dtype=torch.int32).pin_memory(),
+              torch.empty(int(j.llr.shape[0]), dtype=torch.uint8).pin_memory()) for j in jobs]
+
+    def step():
+        for j, (hl, hs) in zip(jobs, h_in):
+            j.llr.copy_(hl, non_blocking=True)
+            j.syn.copy_(hs, non_blocking=True)
+        outs = dec(jobs)
+        for o, (hb, hi, hc) in zip(outs, h_out):
+            hb.copy_(o.bits, non_blocking=True)
+            hi.copy_(o.iterations, non_blocking=True)
+            hc.copy_(o.converged, non_blocking=True)
+
+    ms = timed_plain(step, steps) / steps
+    bits = sum(int(j.llr.shape[0]) * int(j.llr.shape[1]) for j in jobs)
+    moved = sum(hl.numel() * 4 + hs.numel() + hb.numel() + 5 * hi.numel()
+                for (hl, hs), (hb, hi, _) in zip(h_in, h_out))
+    return {"ms_per_step": round(ms, 3), "value": round(bits / (ms * 1e-3) / 1e6, 3),
+            "host_device_bytes_per_step": moved}
+
+
 def run_mix(args, cpu) -> dict:
     import numpy as np
     import torch
@@ -288,7 +338,7 @@ def run_mix(args, cpu) -> dict:
     jobs, truth = [], []
     for prof in MIX:
         code = met.Code.build(PROFILES[prof], n, CODE_SEED[prof])
-        snr = args.snr if args.snr is not None else BJ_SNR[prof]
+        snr = job_snr(args, prof)
         bits, llr = make_frames(n, B, snr, FRAME_SEED)
         syn = met.syndrome(code, torch.from_numpy(bits).to(dev))
         budget = args.max_iter if args.max_iter is not None else ITER_BUDGET[prof]
@@ -322,6 +372,8 @@ def run_mix(args, cpu) -> dict:
     same = all(np.array_equal(a.bits.cpu().numpy(), b.bits.cpu().numpy())
                and np.array_equal(a.iterations.cpu().numpy(), b.iterations.cpu().numpy())
                for a, b in zip(p_out, b_out))
+    e2e = end_to_end(jobs, dec, min(args.steps, 3))
+    copy_gbps = copy_bandwidth()
 
     total_bits = B * n * len(jobs) * args.steps
     b_val = total_bits / (b_ms * 1e-3) / 1e6
@@ -337,8 +389,7 @@ def run_mix(args, cpu) -> dict:
         for k, v in cls.items():
             check_bytes[k] = check_bytes.get(k, 0.0) + v
         var_bytes += var
-        d = {"profile": prof, "snr": float(args.snr if args.snr is not None else BJ_SNR[prof]),
-             "max_iter": j.max_iter}
+        d = {"profile": prof, "snr": float(job_snr(args, prof)), "max_iter": j.max_iter}
         d.update(fer_summary(o, bits))
         d["plain_fer"] = fer_summary(p_out[len(per_job)], bits)["fer"]
         per_job.append(d)
@@ -366,6 +417,10 @@ def run_mix(args, cpu) -> dict:
                   "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)}
                                  for k, v in p_kt.items()}},
         "batched_over_plain": round(b_val / p_val, 4),
+        "end_to_end_with_host_copies": e2e,
+        "measured_copy_GBps": round(copy_gbps, 1),
+        "frac_of_measured_copy": {"k_persistent": round(roof["achieved"] / copy_gbps, 4),
+                                  "k_check<3,1>": round(plain_roof["achieved"] / copy_gbps, 4)},
         "graph_replay": {"value": round(total_bits / (g_ms * 1e-3) / 1e6, 3),
                          "ms_per_step": round(g_ms / args.steps, 3)},
         "identical_outputs": bool(same),
@@ -384,7 +439,7 @@ def run_single(args, cpu) -> dict:
     import paper_1711_01783_amd as met
 
     prof = args.profile
-    snr = args.snr if args.snr is not None else BJ_SNR[prof]
+    snr = job_snr(args, prof)
     max_iter = args.max_iter if args.max_iter is not None else ITER_BUDGET[prof]
     n, B = args.n, args.frames
     dev = torch.device("cuda:0")
@@ -399,7 +454,10 @@ def run_single(args, cpu) -> dict:
         return met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
                           check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
 
-    ms, kt, out = timed(step, args.steps, args.warmup)
+    ms_ev, kt, out = timed(step, args.steps, args.warmup)
+    # throughput from a pass without the per-launch events (they cost the
+    # launch-bound small cases much of their time)
+    ms = timed_plain(step, args.steps)
     value = B * n * args.steps / (ms * 1e-3) / 1e6
     W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 32 if B <= 32 else 64
     early = not args.fixed_iters
@@ -412,6 +470,7 @@ def run_single(args, cpu) -> dict:
     rec = {
         "value": round(value, 3),
         "ms_per_step": round(ms / args.steps, 3),
+        "ms_per_step_with_launch_timing": round(ms_ev / args.steps, 3),
         "config": {
             "workload": "plain BP (one decode call per batch), rate %s MET profile, N=%d, %d frames, SNR %g, "
             "max %d iterations, %s" % (PROFILES[prof].rate, n, B, snr, max_iter,
@@ -423,6 +482,28 @@ def run_single(args, cpu) -> dict:
         "kernels_us": {k: {"launches": v[0], "avg_us": round(1e3 * v[1] / max(1, v[0]), 2)} for k, v in kt.items()},
     }
     rec.update(fer_summary(out, bits))
+    # per iteration of the slowest frame (small cases are launch-bound: this,
+    # not the roofline, is their figure)
+    rec["us_per_iteration"] = round(1e3 * ms / args.steps / max(1, int(out.iterations.max().item())), 2)
+    # the same job through the batched persistent launch (one graph replay per
+    # decode), on the same inputs; outputs must be identical
+    del ws
+    job = [met.Job(code, d_llr, d_syn, max_iter, args.fixed_iters)]
+    dec = met.BatchedDecoder()
+    shape = None if args.no_autotune else dec.autotune(job)  # outside the timed region
+    bout = dec(job)[0]
+    b_ms = timed_plain(lambda: dec(job), args.steps)
+    torch.cuda.synchronize()
+    rec["batched"] = {
+        "value": round(B * n * args.steps / (b_ms * 1e-3) / 1e6, 3),
+        "ms_per_step": round(b_ms / args.steps, 3),
+        "us_per_iteration": round(1e3 * b_ms / args.steps / max(1, int(bout.iterations.max().item())), 2),
+        "identical_outputs": bool(np.array_equal(bout.bits.cpu().numpy(), out.bits.cpu().numpy())
+                                  and np.array_equal(bout.iterations.cpu().numpy(), out.iterations.cpu().numpy())),
+        "wait_expired": bool(dec.barrier_expired()),
+        "autotuned_shape": shape,
+    }
+    rec["batched_over_plain"] = round(rec["batched"]["value"] / rec["value"], 4)
     return rec
 
 
@@ -666,6 +747,9 @@ def main() -> int:
     ap.add_argument("--snr", type=float, default=None, help="override every job's SNR")
     ap.add_argument("--max-iter", type=int, default=None, help="override every job's budget")
     ap.add_argument("--fixed-iters", action="store_true")
+    ap.add_argument("--waterfall", action="store_true",
+                    help="jobs at the waterfall SNRs of their rates (0.19 / 0.10 / 0.065) instead of the "
+                         "workload's operating points")
     ap.add_argument("--check-steps", type=int, default=0, help="check steps per wave (0 = default)")
     ap.add_argument("--vn-chunk", type=int, default=0, help="variable-kernel gathers in flight (0 = default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")

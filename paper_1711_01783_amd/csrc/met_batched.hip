@@ -42,7 +42,8 @@ struct BarrierState {
   uint32_t pad0[31];
   uint32_t gen;    // generation, polled by every block (its own line)
   int32_t err;     // set when a wait expired
-  uint32_t pad1[30];
+  uint32_t stop;   // set with a generation flip when every job has finished
+  uint32_t pad1[29];
 };
 static_assert(sizeof(BarrierState) == 256, "barrier state fills the first 256 bytes");
 
@@ -52,7 +53,8 @@ constexpr int kMaxJobs = 64;
 constexpr int kCounterSets = 3;               // tile counters rotate over phases
 constexpr size_t kOffGroups = 256;
 constexpr size_t kOffTiles = kOffGroups + (size_t)kMaxBarrierGroups * kLine * 4;
-constexpr size_t kControlBytes = kOffTiles + (size_t)kCounterSets * kMaxJobs * kXcds * kLine * 4;
+constexpr size_t kOffCursor = kOffTiles + (size_t)kCounterSets * kMaxJobs * kXcds * kLine * 4;
+constexpr size_t kControlBytes = kOffCursor + (size_t)kMaxJobs * 4;  // + per job: first group maybe running
 constexpr int kMaxGrid = 32 * kXcds * (kMaxBarrierGroups / kXcds);  // 2048 blocks
 
 constexpr uint32_t kSpinLimit = 1u << 21;  // polls of about 1 us each (load + sleep)
@@ -73,8 +75,12 @@ __device__ __forceinline__ uint32_t *tile_counter(char *ctl, int set, int job, i
 // device scope (release) and, after the flip, invalidates its caches
 // (acquire), which the block's other waves, held at the block barrier, share.
 // The wait is bounded; on expiry the error flag is set, every later barrier
-// returns at once and the caller stops.  Returns the error flag.
-__device__ int grid_barrier(char *ctl, uint32_t nblocks) {
+// returns at once and the caller stops.  The last arrival also evaluates
+// done() (with every block's writes visible) and publishes the result with the
+// flip, so every block takes the same decision.  Returns non-zero when the
+// caller must stop (a wait expired, or done() held).
+template <class Done>
+__device__ int grid_barrier(char *ctl, uint32_t nblocks, Done done) {
   __shared__ int s_err;
   BarrierState *b = reinterpret_cast<BarrierState *>(ctl);
   __builtin_amdgcn_s_waitcnt(0);
@@ -97,6 +103,7 @@ __device__ int grid_barrier(char *ctl, uint32_t nblocks) {
     if (last) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&b->stop, done() ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       uint32_t spins = 0;
@@ -112,7 +119,8 @@ __device__ int grid_barrier(char *ctl, uint32_t nblocks) {
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    s_err = __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_err = __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+            (int)__hip_atomic_load(&b->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   return s_err;
@@ -300,7 +308,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
       }
       __syncthreads();
     }
-    if (grid_barrier(ctl, gridDim.x)) return;  // barrier expired: results are invalid, stop
+    // Every job finished: its phases are over, or (early exit) all its frames
+    // have retired, after which its tiles would change nothing (masks only
+    // shrink, and the output kernels skip retired frames).  Groups below a
+    // job's cursor are known to be empty.
+    auto all_done = [&]() {
+      int32_t *first = reinterpret_cast<int32_t *>(ctl + kOffCursor);
+      for (int j = 0; j < n_jobs; ++j) {
+        if (phase + 1 - jobs[j].offset >= 2 * jobs[j].max_iter) continue;
+        if (!jobs[j].early) return false;
+        const uint64_t *act = jobs[j].vp.active;
+        int g = __hip_atomic_load(first + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (g < jobs[j].G && __hip_atomic_load(act + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0ull) ++g;
+        __hip_atomic_store(first + j, g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (g < jobs[j].G) return false;
+      }
+      return true;
+    };
+    // a wait expired (results invalid), or every job finished
+    if (grid_barrier(ctl, gridDim.x, all_done)) return;
   }
 }
 

@@ -96,6 +96,23 @@ def test_single_job_and_different_job_sets(mix):
         _same(out, _plain(jobs), str(sel))
 
 
+def test_launch_stops_when_every_frame_has_converged():
+    """Jobs whose frames all converge long before their budgets: the launch
+    stops at the first barrier after the last frame retired (outputs equal the
+    plain decode's, which runs every iteration), also next to a job with more
+    work left and next to a fixed-iteration job."""
+    easy = [_job("r0.1", 4096, 64, 0.5, 300, 21)[0], _job("r0.02", 4096, 3, 0.2, 400, 22)[0]]
+    slow = _job("r0.05", 8192, 20, 0.10, 60, 23)[0]
+    fixed = _job("r0.1", 4096, 8, 0.5, 40, 24, fixed=True)[0]
+    for sel in (easy, easy + [slow], [fixed] + easy):
+        out = met.decode_batched(sel)
+        torch.cuda.synchronize()
+        ref = _plain(sel)
+        _same(out, ref, "stop")
+    conv = [o.converged.cpu().numpy() for o in _plain(easy)]
+    assert all(c.all() for c in conv)
+
+
 def test_tree_codes_with_runtime_degree_checks():
     from tests.trees import random_tree
     from oracle import code as oc
