@@ -447,12 +447,14 @@ def run_single(args, cpu) -> dict:
     bits, llr = make_frames(n, B, snr, FRAME_SEED)
     d_llr = torch.from_numpy(llr).to(dev)
     d_syn = met.syndrome(code, torch.from_numpy(bits).to(dev))
-    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters) + 256, dtype=torch.uint8, device=dev)
+    half = args.c2v_fp16
+    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters, c2v_fp16=half) + 256, dtype=torch.uint8,
+                     device=dev)
     torch.cuda.synchronize()
 
     def step():
         return met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
-                          check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
+                          check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk, c2v_fp16=half)
 
     ms_ev, kt, out = timed(step, args.steps, args.warmup)
     # throughput from a pass without the per-launch events (they cost the
@@ -485,6 +487,9 @@ def run_single(args, cpu) -> dict:
     # per iteration of the slowest frame (small cases are launch-bound: this,
     # not the roofline, is their figure)
     rec["us_per_iteration"] = round(1e3 * ms / args.steps / max(1, int(out.iterations.max().item())), 2)
+    if half:  # the batched form stores float messages only
+        rec["config"]["c2v_storage"] = "fp16"
+        return rec
     # the same job through the batched persistent launch (one graph replay per
     # decode), on the same inputs; outputs must be identical
     del ws
@@ -747,6 +752,8 @@ def main() -> int:
     ap.add_argument("--snr", type=float, default=None, help="override every job's SNR")
     ap.add_argument("--max-iter", type=int, default=None, help="override every job's budget")
     ap.add_argument("--fixed-iters", action="store_true")
+    ap.add_argument("--c2v-fp16", action="store_true",
+                    help="single: check-to-variable messages stored in half precision (MET_C2V_FP16)")
     ap.add_argument("--waterfall", action="store_true",
                     help="jobs at the waterfall SNRs of their rates (0.19 / 0.10 / 0.065) instead of the "
                          "workload's operating points")

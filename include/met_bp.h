@@ -60,6 +60,13 @@ extern "C" {
                                a quarter of the occupied groups; results are
                                identical either way; no compaction when
                                posteriors are requested) */
+#define MET_C2V_FP16 8u     /* check-to-variable messages stored as IEEE half
+                               (rounded to nearest; all arithmetic in float):
+                               half the message bytes.  Groups of 64 frames
+                               only (B > 32), no compaction.  Results are not
+                               those of the float decoder; its gate is the
+                               frame error rate (within the 95 % interval of
+                               the float decoder's on the same frames) */
 #define MET_NO_DEG1_SKIP 4u /* degree-1 variable nodes take part in every
                                iteration like the others (their check messages
                                are stored and their posteriors updated; the
@@ -175,8 +182,8 @@ int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int
  *   llr:       dev float32 [B][N], 4-byte aligned
  *   syn:       dev uint8   [B][M]
  *   max_iter:  >= 1
- *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS, optionally | MET_NO_COMPACT
- *              and/or | MET_NO_DEG1_SKIP
+ *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS, optionally | MET_NO_COMPACT,
+ *              | MET_NO_DEG1_SKIP and/or | MET_C2V_FP16
  *   bits:      dev uint8 [B][N] output, hard decisions at each frame's stop
  *   iters:     dev int32 [B] output, iterations run (1..max_iter)
  *   converged: dev uint8 [B] output, 1 iff H bits = syn

@@ -16,6 +16,7 @@ MET_EARLY_EXIT = 0
 MET_FIXED_ITERS = 1
 MET_NO_COMPACT = 2
 MET_NO_DEG1_SKIP = 4
+MET_C2V_FP16 = 8
 MET_MAX_EDGE_TYPES = 8
 
 _ERRNAMES = {MET_EINVAL: "MET_EINVAL", MET_ENOMEM: "MET_ENOMEM", MET_EHIP: "MET_EHIP", MET_ESTATE: "MET_ESTATE"}

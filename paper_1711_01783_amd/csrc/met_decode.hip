@@ -198,7 +198,9 @@ struct Decoder {
   template <typename T>
   T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 
-  template <int W>
+  // CT: storage type of the check-to-variable messages (float, or half_t for
+  // MET_C2V_FP16; the arithmetic is float either way).
+  template <int W, typename CT = float>
   int run(const float *llr, const uint8_t *syn, int max_iter, uint32_t flags, uint8_t *bits, int32_t *iters,
           uint8_t *conv, float *post, const float *weights, int32_t wstride) {
     const int G = pl.G;
@@ -284,7 +286,9 @@ struct Decoder {
     const unsigned vn_blocks = (unsigned)((c->N2 + vn_per_block - 1) / vn_per_block);
     const bool early = !(flags & MET_FIXED_ITERS);
     const bool special = post || weights;
-    const bool compact = W == 64 && G > 1 && early && !special && !(flags & MET_NO_COMPACT);
+    // (compaction moves float message rows: not with half-precision storage)
+    const bool compact = W == 64 && G > 1 && early && !special && !(flags & MET_NO_COMPACT) &&
+                         std::is_same<CT, float>::value;
     int32_t *slot_frame = compact ? at<int32_t>(pl.off_slot) : nullptr;
     int32_t *ctab = at<int32_t>(pl.off_ctab);
     vp.slot_frame = slot_frame;
@@ -324,7 +328,7 @@ struct Decoder {
       for (size_t k = 0; k < classes.size(); ++k) {
         cp.unsat_clear = k == 0 ? unsat + (size_t)(it & 1) * G : nullptr;
         ScopedTimer t(st, kCheckKernelName[classes[k].shape]);
-        launch_check<W>(cp, classes[k], mode, cn_ipw, G, st);
+        launch_check<W, CT>(cp, classes[k], mode, cn_ipw, G, st);
       }
       vp.it = it;
       vp.retire = early && it >= 2;
@@ -333,11 +337,11 @@ struct Decoder {
         ScopedTimer t(st, "k_variable");
         const dim3 grid(vn_blocks, G);
         if (vn_chunk == 32)
-          hipLaunchKernelGGL((k_variable<W, 32>), grid, dim3(kBlock), 0, st, vp);
+          hipLaunchKernelGGL((k_variable<W, 32, CT>), grid, dim3(kBlock), 0, st, vp);
         else if (vn_chunk == 16)
-          hipLaunchKernelGGL((k_variable<W, 16>), grid, dim3(kBlock), 0, st, vp);
+          hipLaunchKernelGGL((k_variable<W, 16, CT>), grid, dim3(kBlock), 0, st, vp);
         else
-          hipLaunchKernelGGL((k_variable<W, 8>), grid, dim3(kBlock), 0, st, vp);
+          hipLaunchKernelGGL((k_variable<W, 8, CT>), grid, dim3(kBlock), 0, st, vp);
       }
       if (compact && it % kCompactEvery == 0 && max_iter - it >= kCompactMinLeft) {
         ScopedTimer t(st, "k_compact");
@@ -493,10 +497,14 @@ extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, u
 static int validate_decode(const met_code *c, int32_t B, uint32_t flags) {
   if (!c) return fail(MET_EINVAL, "NULL code");
   if (B < 1 || B > 65535) return fail(MET_EINVAL, "B = %d outside 1..65535", B);
-  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT | MET_NO_DEG1_SKIP))
+  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT | MET_NO_DEG1_SKIP | MET_C2V_FP16))
     return fail(MET_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & MET_C2V_FP16) && met::choose_interleave(B) != 64)
+    return fail(MET_EINVAL, "MET_C2V_FP16 needs groups of 64 frames (B > 32), B = %d", B);
   return MET_OK;
 }
+
+static size_t c2v_bytes(uint32_t flags) { return (flags & MET_C2V_FP16) ? sizeof(met::half_t) : sizeof(float); }
 
 // The layout a decode with these flags runs on: the code's own, or its view
 // with degree-1 variable nodes iterated.
@@ -514,7 +522,7 @@ extern "C" int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t
   if (!bytes) return fail(MET_EINVAL, "NULL bytes");
   rc = decode_layout(c, flags, &c);
   if (rc) return rc;
-  *bytes = met::make_plan(c, B, want_posterior != 0, false, met::choose_interleave(B)).total;
+  *bytes = met::make_plan(c, B, want_posterior != 0, false, met::choose_interleave(B), c2v_bytes(flags)).total;
   return MET_OK;
 }
 
@@ -543,12 +551,14 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
   rc = decode_layout(c, flags, &c);
   if (rc) return rc;
   const int W = met::choose_interleave(B);
-  const met::Plan pl = met::make_plan(c, B, posterior != nullptr, false, W);
+  const met::Plan pl = met::make_plan(c, B, posterior != nullptr, false, W, c2v_bytes(flags));
   if (ws_bytes < pl.total) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, pl.total);
   const met::DeviceCode *d = nullptr;
   rc = met::device_code(c, &d);
   if (rc) return rc;
   met::Decoder dec{c, d, pl, static_cast<char *>(workspace), (hipStream_t)stream, B, ipw, chunk};
+  if (flags & MET_C2V_FP16)
+    return dec.run<64, met::half_t>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   switch (W) {
     case 1: return dec.run<1>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     case 4: return dec.run<4>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "met_internal.h"
@@ -62,6 +63,19 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr float kLlrMax = 30.0f;
 constexpr int kXcds = 8;  // accelerator dies; the hardware deals block b to die b mod 8
+
+// Storage of check-to-variable messages: float, or IEEE half (MET_C2V_FP16),
+// converted to float on load and rounded to nearest on store; the arithmetic
+// is float either way.
+using half_t = _Float16;
+template <typename CT>
+__device__ __forceinline__ float ld_c2v(const float *base, int64_t i) {
+  return (float)reinterpret_cast<const CT *>(base)[i];
+}
+template <typename CT>
+__device__ __forceinline__ void st_c2v(float *base, int64_t i, float v) {
+  reinterpret_cast<CT *>(base)[i] = (CT)v;
+}
 
 enum : int32_t {
   F_FIRST = 1,     // iteration 1: P = L, c2v = 0
@@ -235,7 +249,7 @@ __device__ __forceinline__ uint64_t ld_racy(const uint64_t *p, int64_t i) {
 // Check update of one class of checks with a compile-time shape (NM message
 // edges, NL leaf edges per check).  Each wave takes IPW consecutive steps of
 // 64/W checks; all loads of its checks are issued before any arithmetic.
-template <int W, int NM, int NL, int MODE, int IPW, bool PERSIST>
+template <int W, int NM, int NL, int MODE, int IPW, bool PERSIST, typename CT = float>
 __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const ClassArgs &c, int64_t bx, int g) {
   constexpr int D = NM + NL;
   constexpr int IPWAVE = 64 / W;
@@ -271,7 +285,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     for (int m = 0; m < NM; ++m) {
       const int32_t vi = ldro(p.edge_msgvn, m0 + m);
       pv[k][m] = p.Pin[((int64_t)g * p.N2 + vi) * W + w];
-      cv[k][m] = first ? 0.0f : p.c2v_in[((int64_t)g * p.E12 + m0 + m) * W + w];
+      cv[k][m] = first ? 0.0f : ld_c2v<CT>(p.c2v_in, ((int64_t)g * p.E12 + m0 + m) * W + w);
     }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -320,7 +334,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
       const float mag = phi(S[m]);
       float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
       if (weighted) out *= ldro(p.weights, (int64_t)ldro(p.edge_type, m0 + m) * p.wstride + (p.it - 1));
-      if (store) p.c2v[((int64_t)g * p.E12 + m0 + m) * W + w] = out;
+      if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
     }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
@@ -352,15 +366,15 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
   }
 }
 
-template <int W, int NM, int NL, int MODE, int IPW>
+template <int W, int NM, int NL, int MODE, int IPW, typename CT = float>
 __global__ __launch_bounds__(kBlock) void k_check_fixed(const CheckParams p, const ClassArgs c) {
   const GridTile t = MODE == M_SPECIAL ? GridTile{blockIdx.x, (int)blockIdx.y} : xcd_grid_tile();
-  check_fixed_body<W, NM, NL, MODE, IPW, false>(p, c, t.bx, t.g);
+  check_fixed_body<W, NM, NL, MODE, IPW, false, CT>(p, c, t.bx, t.g);
 }
 
 // Check update with run-time degrees (total degree <= MET_MAX_CHECK_DEGREE),
 // for classes without a compiled shape.  One check per lane group.
-template <int W, bool PERSIST>
+template <int W, bool PERSIST, typename CT = float>
 __device__ __forceinline__ void check_generic_body(const CheckParams &p, const ClassArgs &c, int64_t bx, int g) {
   constexpr int D = MET_MAX_CHECK_DEGREE;
   clear_next_unsat(p, bx, g);
@@ -387,7 +401,7 @@ __device__ __forceinline__ void check_generic_body(const CheckParams &p, const C
     if (k < nm) {
       const int64_t e = m0 + k;
       const float pv = p.Pin[((int64_t)g * p.N2 + p.edge_msgvn[e]) * W + w];
-      const float cv = first ? 0.0f : p.c2v_in[((int64_t)g * p.E12 + e) * W + w];
+      const float cv = first ? 0.0f : ld_c2v<CT>(p.c2v_in, ((int64_t)g * p.E12 + e) * W + w);
       parity ^= (uint32_t)(pv < 0.0f);
       const float x = clamp_llr(pv - cv);
       A[k] = phi(fabsf(x));
@@ -416,7 +430,7 @@ __device__ __forceinline__ void check_generic_body(const CheckParams &p, const C
       const float mag = phi(pre[k] + suf[k]);
       float out = ((tot ^ (neg >> k)) & 1u) ? -mag : mag;
       if (weighted) out *= p.weights[(int64_t)p.edge_type[m0 + k] * p.wstride + (p.it - 1)];
-      if (store) p.c2v[((int64_t)g * p.E12 + m0 + k) * W + w] = out;
+      if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + k) * W + w, out);
     }
   }
   // Leaf decisions: ballots must be executed by every lane of the wave, so the
@@ -462,10 +476,10 @@ __device__ __forceinline__ void check_generic_body(const CheckParams &p, const C
   }
 }
 
-template <int W>
+template <int W, typename CT = float>
 __global__ __launch_bounds__(kBlock) void k_check_generic(const CheckParams p, const ClassArgs c) {
   const GridTile t = xcd_grid_tile();
-  check_generic_body<W, false>(p, c, t.bx, t.g);
+  check_generic_body<W, false, CT>(p, c, t.bx, t.g);
 }
 
 // Syndrome test only (after the last iteration): parity of the hard decisions
@@ -520,7 +534,7 @@ __device__ __forceinline__ int lane_frame(const int32_t *slot_frame, int g, int 
 
 // Variable update: P_v = L_v + sum of c2v over v's message edges (gathered U
 // at a time, summed in list order).
-template <int W, int U, bool PERSIST>
+template <int W, int U, bool PERSIST, typename CT = float>
 __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, int g) {
   uint64_t act = ld_racy<PERSIST>(p.active, g);
   if (p.retire) {
@@ -551,12 +565,12 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
   if (i >= p.N2) return;
   const int32_t e0 = ldro(p.vn_ptr, i), e1 = ldro(p.vn_ptr, i + 1);
   float P = p.L2[((int64_t)g * p.N2 + i) * W + w];
-  const float *c2v = p.c2v + (int64_t)g * p.E12 * W + w;
+  const CT *c2v = reinterpret_cast<const CT *>(p.c2v) + (int64_t)g * p.E12 * W + w;
   int32_t e = e0;
   for (; e + U <= e1; e += U) {
     float a[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) a[u] = c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
+    for (int u = 0; u < U; ++u) a[u] = (float)c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
 #pragma unroll
     for (int u = 0; u < U; ++u) P += a[u];
   }
@@ -564,18 +578,18 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
     for (; e + 8 <= e1; e += 8) {
       float a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
+      for (int u = 0; u < 8; ++u) a[u] = (float)c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
 #pragma unroll
       for (int u = 0; u < 8; ++u) P += a[u];
     }
-  for (; e < e1; ++e) P += c2v[(int64_t)ldro(p.vn_edges, e) * W];
+  for (; e < e1; ++e) P += (float)c2v[(int64_t)ldro(p.vn_edges, e) * W];
   if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
 }
 
-template <int W, int U>
+template <int W, int U, typename CT = float>
 __global__ __launch_bounds__(kBlock) void k_variable(const VarParams p) {
   const GridTile t = xcd_grid_tile();
-  variable_body<W, U, false>(p, t.bx, t.g);
+  variable_body<W, U, false, CT>(p, t.bx, t.g);
 }
 
 // ----------------------------------------------------------------------------
@@ -770,7 +784,7 @@ int choose_interleave(int B) {
   return 64;
 }
 
-Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
+Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W, size_t c2v_bytes = sizeof(float)) {
   Plan pl;
   pl.W = W;
   pl.G = (B + W - 1) / W;
@@ -782,7 +796,7 @@ Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
     return at;
   };
   // c2v also serves as the staging area of the input transpose.
-  pl.off_c2v = take(std::max<size_t>(GW * c->E12, GW * c->N) * sizeof(float));
+  pl.off_c2v = take(std::max<size_t>(GW * c->E12 * c2v_bytes, GW * c->N * sizeof(float)));
   pl.off_P = take(GW * c->N2 * sizeof(float));
   pl.off_L2 = take(GW * c->N2 * sizeof(float));
   pl.off_Lphi = take(GW * c->EL * sizeof(float));
@@ -806,17 +820,17 @@ Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W) {
     if (e_ != hipSuccess) return fail(MET_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-template <int W, int MODE, int IPW>
+template <int W, int MODE, int IPW, typename CT = float>
 void launch_fixed(int shape, unsigned blocks, int G, hipStream_t st, const CheckParams &p, const ClassArgs &c) {
   const dim3 grid(blocks, G), block(kBlock);
   switch (shape) {
-    case 0: hipLaunchKernelGGL((k_check_fixed<W, 3, 1, MODE, IPW>), grid, block, 0, st, p, c); break;
-    case 1: hipLaunchKernelGGL((k_check_fixed<W, 2, 1, MODE, IPW>), grid, block, 0, st, p, c); break;
-    case 2: hipLaunchKernelGGL((k_check_fixed<W, 12, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
-    case 3: hipLaunchKernelGGL((k_check_fixed<W, 11, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
-    case 4: hipLaunchKernelGGL((k_check_fixed<W, 6, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
-    case 5: hipLaunchKernelGGL((k_check_fixed<W, 5, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
-    default: hipLaunchKernelGGL((k_check_fixed<W, 4, 0, MODE, IPW>), grid, block, 0, st, p, c); break;
+    case 0: hipLaunchKernelGGL((k_check_fixed<W, 3, 1, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
+    case 1: hipLaunchKernelGGL((k_check_fixed<W, 2, 1, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
+    case 2: hipLaunchKernelGGL((k_check_fixed<W, 12, 0, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
+    case 3: hipLaunchKernelGGL((k_check_fixed<W, 11, 0, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
+    case 4: hipLaunchKernelGGL((k_check_fixed<W, 6, 0, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
+    case 5: hipLaunchKernelGGL((k_check_fixed<W, 5, 0, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
+    default: hipLaunchKernelGGL((k_check_fixed<W, 4, 0, MODE, IPW, CT>), grid, block, 0, st, p, c); break;
   }
 }
 
@@ -832,15 +846,24 @@ void launch_fixed_ipw(int ipw, int shape, unsigned blocks, int G, hipStream_t st
 }
 
 // One check-kernel launch over a class: compiled shape (mode, steps per wave)
-// or the run-time-degree kernel.
-template <int W>
+// or the run-time-degree kernel.  Half-precision message storage is compiled
+// for groups of 64 frames with 4 check steps per wave only.
+template <int W, typename CT = float>
 void launch_check(const CheckParams &p, const ClassArgs &a, int mode, int cn_ipw, int G, hipStream_t st) {
+  constexpr bool half = std::is_same<CT, half_t>::value;
+  static_assert(!half || W == 64, "half-precision messages need groups of 64 frames");
   const bool gen = a.shape == kShapeGeneric;
-  const int ipw = (W == 64 && !gen) ? cn_ipw : 1;
+  const int ipw = (W == 64 && !gen) ? (half ? 4 : cn_ipw) : 1;
   const int64_t per_block = (int64_t)kWavesPerBlock * ipw * (64 / W);
   const unsigned blocks = (unsigned)((a.n_checks + per_block - 1) / per_block);
   if (gen)
-    hipLaunchKernelGGL(k_check_generic<W>, dim3(blocks, G), dim3(kBlock), 0, st, p, a);
+    hipLaunchKernelGGL((k_check_generic<W, CT>), dim3(blocks, G), dim3(kBlock), 0, st, p, a);
+  else if (half && mode == M_SPECIAL)
+    launch_fixed<W, M_SPECIAL, 4, CT>(a.shape, blocks, G, st, p, a);
+  else if (half && mode == M_FIRST)
+    launch_fixed<W, M_FIRST, 4, CT>(a.shape, blocks, G, st, p, a);
+  else if (half)
+    launch_fixed<W, M_MAIN, 4, CT>(a.shape, blocks, G, st, p, a);
   else if (mode == M_SPECIAL)
     launch_fixed_ipw<W, M_SPECIAL>(ipw, a.shape, blocks, G, st, p, a);
   else if (mode == M_FIRST)

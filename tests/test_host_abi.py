@@ -110,7 +110,7 @@ def test_decode_argument_validation_without_gpu():
     dummy = P(256)
     n = ctypes.c_size_t()
     assert L.met_decode_workspace_bytes(c.handle, 0, 0, 0, ctypes.byref(n)) == -1
-    assert L.met_decode_workspace_bytes(c.handle, 64, 8, 0, ctypes.byref(n)) == -1
+    assert L.met_decode_workspace_bytes(c.handle, 64, 16, 0, ctypes.byref(n)) == -1
     assert L.met_decode_workspace_bytes(None, 64, 0, 0, ctypes.byref(n)) == -1
     assert L.met_decode_workspace_bytes(c.handle, 64, 0, 0, ctypes.byref(n)) == 0 and n.value > 0
     big = n.value
@@ -128,7 +128,7 @@ def test_decode_argument_validation_without_gpu():
     assert call(llr=P(258)) == -1          # misaligned float buffer
     assert call(ws=P(264)) == -1           # workspace not 256-byte aligned
     assert call(wsb=big - 1) == -1         # too small
-    assert call(flags=8) == -1
+    assert call(flags=16) == -1
     assert "flags" in L.met_last_error().decode()
     assert call(flags=4) == -1             # the all-VN layout needs a larger workspace
     assert "workspace" in L.met_last_error().decode()
@@ -157,6 +157,16 @@ def test_all_vn_layout_sizes():
     assert c.info() == info
     # the extra bytes are at least the degree-1 nodes' check messages and rows
     assert b - a >= 64 * 4 * info["n_deg1"]
+
+
+def test_fp16_messages_flag():
+    """MET_C2V_FP16 halves the message array and needs groups of 64 frames."""
+    code = met.Code.build(PROFILES["r0.1"], 4096, 5)
+    with pytest.raises(met.MetError):
+        met.workspace_bytes(code, 32, c2v_fp16=True)
+    info = code.info()
+    full, half = met.workspace_bytes(code, 64), met.workspace_bytes(code, 64, c2v_fp16=True)
+    assert full - half >= 2 * 64 * info["n_msg_edges"] - 4096
 
 
 def test_free_is_idempotent():
