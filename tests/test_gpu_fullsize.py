@@ -78,3 +78,78 @@ def test_full_size_properties_at_waterfall():
     for a, b in ((plain.bits, batched.bits), (plain.iterations, batched.iterations),
                  (plain.converged, batched.converged)):
         np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_batched_mix_at_full_size_equals_plain():
+    """The benchmark's batched launch itself: the three codes at N = 10^6, 64
+    frames each, budgets 100 / 150 / 200, early exit, autotuned launch shape;
+    every job's bits, iteration counts and flags equal the plain decode's."""
+    jobs = []
+    for prof, budget in (("r0.1", 100), ("r0.05", 150), ("r0.02", 200)):
+        code = met.Code.build(PROFILES[prof], N, SEED[prof])
+        bits, llr = make_frames(N, B, BJ_SNR[prof], 5000)
+        syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
+        jobs.append(met.Job(code, torch.from_numpy(llr).to(DEV), syn, budget))
+    dec = met.BatchedDecoder()
+    print("autotune", dec.autotune(jobs), flush=True)
+    out = dec(jobs)
+    ref = [met.decode(j.code, j.llr, j.syn, j.max_iter) for j in jobs]
+    torch.cuda.synchronize()
+    assert not dec.barrier_expired()
+    for k, (a, b) in enumerate(zip(out, ref)):
+        for x, y in ((a.bits, b.bits), (a.iterations, b.iterations), (a.converged, b.converged)):
+            np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy(), err_msg="job %d" % k)
+
+
+def test_weighted_bp_at_full_size():
+    """Weighted BP in the benchmark's configuration (rate 0.02, N = 10^6, 128
+    frames, two groups of 64): with unit scales over 200 iterations the forward
+    pass equals plain decoding bit for bit; with non-unit scales over 3
+    iterations, on 128 copies of one frame (so the mean loss is that frame's),
+    posteriors and gradient match the FP64 oracle on that frame; the gradient
+    does not depend on the checkpoint interval, and scales of leaf edges get
+    none before the last iteration."""
+    from paper_1711_01783_amd import wbp
+    from oracle import wbp as owbp
+
+    prof, b = "r0.02", 128
+    code_g = met.Code.build(PROFILES[prof], N, SEED[prof])
+    bits, llr = make_frames(N, b, BJ_SNR[prof], 5000)
+    d_llr = torch.from_numpy(llr).to(DEV)
+    d_syn = met.syndrome(code_g, torch.from_numpy(bits).to(DEV))
+    T = code_g.info()["n_edge_types"]
+    print("unit scales, 200 iterations", flush=True)
+    post, b1, c1, ws = wbp.forward(code_g, d_llr, d_syn, torch.ones(T, 200, device=DEV), 15)
+    out = met.decode(code_g, d_llr, d_syn, 200, fixed_iters=True, posterior=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(post.cpu().numpy(), out.posterior.cpu().numpy())
+    np.testing.assert_array_equal(b1.cpu().numpy(), out.bits.cpu().numpy())
+    del post, out, ws
+    torch.cuda.empty_cache()
+
+    print("gradient on one frame, 3 iterations", flush=True)
+    it = 3
+    w = (1.0 + 0.1 * np.random.default_rng(0).standard_normal((T, it))).astype(np.float32)
+    x1, l1 = bits[:1], llr[:1]
+    rep_l = torch.from_numpy(np.repeat(l1, b, axis=0)).to(DEV)
+    rep_s = met.syndrome(code_g, torch.from_numpy(np.repeat(x1, b, axis=0)).to(DEV))
+    sgn = torch.from_numpy(np.repeat(1.0 - 2.0 * x1.astype(np.float32), b, axis=0)).to(DEV)
+    grads = []
+    for k in (1, 2):
+        wt = torch.from_numpy(w).to(DEV).requires_grad_(True)
+        p = wbp.weighted_bp(wt, code_g, rep_l, rep_s, k)
+        torch.nn.functional.softplus(-sgn * p).mean().backward()
+        torch.cuda.synchronize()
+        grads.append(wt.grad.cpu().numpy())
+        p_gpu = p.detach()[0].cpu().numpy()
+    np.testing.assert_array_equal(grads[0], grads[1])
+    g = grads[0]
+    assert np.all(g[2, :-1] == 0.0)
+    code_o = oc.build(PROFILES[prof], N, SEED[prof])
+    s1 = oc.syndrome(code_o, x1)
+    _, g_ref = owbp.loss_and_grad(code_o, l1, s1, x1, w.astype(np.float64), it)
+    p_ref = owbp.posteriors(code_o, l1, s1, w.astype(np.float64), it)[0]
+    assert np.all(np.abs(p_gpu - p_ref) <= 1e-3 * np.abs(p_ref) + 1e-4)
+    scale = np.abs(g_ref).max()
+    print("gradient scale %.3g, worst difference %.3g" % (scale, np.abs(g - g_ref).max()), flush=True)
+    np.testing.assert_allclose(g, g_ref, rtol=2e-3, atol=2e-4 * scale)
