@@ -256,7 +256,10 @@ typedef struct {
   int32_t blocks_per_cu;        /* batched: resident blocks per compute unit
                                    (0 = as many as fit) */
   uint32_t batch_flags;         /* batched: MET_BATCH_* */
-  int32_t reserved[4];          /* must be 0 */
+  int32_t interleave;           /* batched: frames per group, 16, 32 or 64
+                                   (one check step per wave below 64);
+                                   default 64 */
+  int32_t reserved[3];          /* must be 0 */
 } met_tuning;
 
 /* met_decode with explicit launch shapes (tuning may be NULL).  Results do not
@@ -301,8 +304,9 @@ int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *workspace, siz
 int met_batched_check(const void *workspace, int32_t *barrier_expired);
 
 /* Autotuner of the batched launch: times candidate launch shapes (check steps
- * per wave 4/2/1 x resident blocks per compute unit 6..2, then the stagger of
- * the fastest) on the same jobs with every budget capped at probe_iters
+ * per wave 4/2/1 x resident blocks per compute unit 6..2 with groups of 64
+ * frames, and blocks per compute unit 6/4/2 with groups of 32 and of 16, then
+ * the stagger of the fastest) on the same jobs with every budget capped at probe_iters
  * iterations (0 selects 6), discards shapes whose barrier expired, and writes
  * the fastest to *best (its time per probe run to *best_ms if not NULL).
  * Synchronises `stream`; overwrites the jobs' outputs.  Results are cached per

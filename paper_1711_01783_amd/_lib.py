@@ -69,7 +69,7 @@ MET_BATCH_NO_GRAPH = 2
 class met_tuning(ctypes.Structure):
     _fields_ = [("check_steps_per_wave", ctypes.c_int32), ("variable_chunk", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("batch_flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("interleave", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class met_job(ctypes.Structure):

@@ -236,13 +236,15 @@ class BatchedDecoder:
 
     Keeps its workspace between calls, so repeated calls with the same jobs
     replay the same cached HIP graph.  check_steps_per_wave / blocks_per_cu /
-    stagger / graph select launch shapes; results do not depend on them."""
+    stagger / graph / interleave (frames per group: 16, 32 or 64) select launch
+    shapes; results do not depend on them."""
 
     def __init__(self, check_steps_per_wave: int = 0, blocks_per_cu: int = 0, stagger: bool = True,
-                 graph: bool = True):
+                 graph: bool = True, interleave: int = 0):
         self.tuning = met_tuning()
         self.tuning.check_steps_per_wave = int(check_steps_per_wave)
         self.tuning.blocks_per_cu = int(blocks_per_cu)
+        self.tuning.interleave = int(interleave)
         self.tuning.batch_flags = (0 if stagger else MET_BATCH_NO_STAGGER) | (0 if graph else MET_BATCH_NO_GRAPH)
         self.workspace = None
         self._ws_ptr = 0
@@ -300,6 +302,7 @@ class BatchedDecoder:
         self.tuning = best
         self.tuning.batch_flags = (best.batch_flags & MET_BATCH_NO_STAGGER) | (0 if graph else MET_BATCH_NO_GRAPH)
         return {"check_steps_per_wave": int(best.check_steps_per_wave), "blocks_per_cu": int(best.blocks_per_cu),
+                "interleave": int(best.interleave),
                 "stagger": not (best.batch_flags & MET_BATCH_NO_STAGGER), "probe_ms": float(ms.value)}
 
     def barrier_expired(self) -> bool:

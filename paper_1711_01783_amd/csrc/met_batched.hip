@@ -20,7 +20,9 @@
 namespace met {
 namespace {
 
-constexpr int kBatchW = 64;
+// Frames per group (interleave width) of a launch: 64 by default; 32 and 16
+// (one check step per wave, as in met_decode) for batches of few frames.
+constexpr int kBatchWidths[] = {64, 32, 16};
 
 struct BatchJob {
   CheckParams cp;  // per-iteration fields are set in the kernel
@@ -136,7 +138,7 @@ using CJob = const BatchJob;  // the host pass only parses device code
 #endif
 
 // Check tile t of job j at iteration l.
-template <int IPW, bool GEN>
+template <int IPW, bool GEN, int W>
 __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) {
   const int32_t cn_tiles = jobs[j].cn_tiles;
   const int64_t g = t / cn_tiles;
@@ -159,26 +161,27 @@ __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) 
   const int gi = (int)g;
   // One compiled mode: c2v starts zero-filled, so iteration 1 needs no variant.
   switch (a.shape) {
-    case 0: check_fixed_body<kBatchW, 3, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 1: check_fixed_body<kBatchW, 2, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 2: check_fixed_body<kBatchW, 12, 0, M_MAIN, I2, true>(p, a, r, gi); break;
-    case 3: check_fixed_body<kBatchW, 11, 0, M_MAIN, I2, true>(p, a, r, gi); break;
-    case 4: check_fixed_body<kBatchW, 6, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 5: check_fixed_body<kBatchW, 5, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 6: check_fixed_body<kBatchW, 4, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 0: check_fixed_body<W, 3, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 1: check_fixed_body<W, 2, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 2: check_fixed_body<W, 12, 0, M_MAIN, I2, true>(p, a, r, gi); break;
+    case 3: check_fixed_body<W, 11, 0, M_MAIN, I2, true>(p, a, r, gi); break;
+    case 4: check_fixed_body<W, 6, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 5: check_fixed_body<W, 5, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 6: check_fixed_body<W, 4, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
     default:
-      if (GEN) check_generic_body<kBatchW, true>(p, a, r, gi);
+      if (GEN) check_generic_body<W, true>(p, a, r, gi);
       break;
   }
 }
 
+template <int W>
 __device__ __forceinline__ void variable_tile(CJob *jobs, int j, int l, int64_t t) {
   VarParams vp = jobs[j].vp;
   const int32_t vb = jobs[j].vn_blocks;
   vp.it = l;
   vp.retire = jobs[j].early && l >= 2;
   vp.unsat = jobs[j].unsat + (size_t)((l - 1) & 1) * jobs[j].G;
-  variable_body<kBatchW, 16, true>(vp, t % vb, (int)(t / vb));
+  variable_body<W, 16, true>(vp, t % vb, (int)(t / vb));
 }
 
 // Phase step of job j: s = phase - offset; even s: check update of iteration
@@ -250,7 +253,7 @@ __device__ int64_t claim(CJob *jobs, int n_jobs, int phase, int xcd, char *ctl, 
 // Run-time-degree checks (GEN) are compiled only into the variant used by
 // batches that hold such classes, which keeps their register arrays out of
 // the common one.
-template <int IPW, bool GEN>
+template <int IPW, bool GEN, int W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_persistent(
     const BatchJob *table, int n_jobs, int n_phases, char *ctl) {
   CJob *jobs = (CJob *)table;
@@ -288,9 +291,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
       int l = 0, kind = 0;
       (void)job_tiles(jobs, j, phase, &l, &kind);
       if (kind == 0)
-        check_tile<IPW, GEN>(jobs, j, l, t);
+        check_tile<IPW, GEN, W>(jobs, j, l, t);
       else
-        variable_tile(jobs, j, l, t);
+        variable_tile<W>(jobs, j, l, t);
       if (leader) {
         int64_t nt = -1;
         if (pj >= 0) {
@@ -347,7 +350,7 @@ struct BatchLayout {
   size_t total = 0;
 };
 
-BatchLayout make_batch_layout(const met_job *jobs, int n) {
+BatchLayout make_batch_layout(const met_job *jobs, int n, int W) {
   BatchLayout L;
   size_t o = 0;
   L.off_barrier = o;
@@ -355,7 +358,7 @@ BatchLayout make_batch_layout(const met_job *jobs, int n) {
   L.off_table = o;
   o += align256(sizeof(BatchJob) * (size_t)n);
   for (int j = 0; j < n; ++j) {
-    Plan p = make_plan(jobs[j].code, jobs[j].B, false, false, kBatchW);
+    Plan p = make_plan(jobs[j].code, jobs[j].B, false, false, W);
     L.off_job.push_back(o);
     o += p.total;
     L.plans.push_back(p);
@@ -404,7 +407,7 @@ struct Batched {
   int n;
   char *ws;
   hipStream_t st;
-  int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1;
+  int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1, W = 64;
   BatchLayout L;
   std::vector<BatchJob> table;
   std::vector<const DeviceCode *> dev;
@@ -413,13 +416,16 @@ struct Batched {
   bool gen = false;  // some class has no compiled shape
 
   const void *kernel() const {
-    if (gen) return (const void *)k_persistent<1, true>;
-    return ipw == 4 ? (const void *)k_persistent<4, false>
-                    : ipw == 2 ? (const void *)k_persistent<2, false> : (const void *)k_persistent<1, false>;
+    if (W == 32) return gen ? (const void *)k_persistent<1, true, 32> : (const void *)k_persistent<1, false, 32>;
+    if (W == 16) return gen ? (const void *)k_persistent<1, true, 16> : (const void *)k_persistent<1, false, 16>;
+    if (gen) return (const void *)k_persistent<1, true, 64>;
+    return ipw == 4 ? (const void *)k_persistent<4, false, 64>
+                    : ipw == 2 ? (const void *)k_persistent<2, false, 64> : (const void *)k_persistent<1, false, 64>;
   }
 
   int prepare() {
-    L = make_batch_layout(jobs, n);
+    if (W != 64) ipw = 1;  // several steps per wave are compiled for groups of 64 only
+    L = make_batch_layout(jobs, n, W);
     dev.resize(n);
     table.resize(n);
     int max_end = 0;
@@ -474,7 +480,8 @@ struct Batched {
       vp.G = pl.G;
       const std::vector<ClassArgs> cls = class_args(c);
       b.n_classes = (int)cls.size();
-      b.vn_blocks = (int32_t)((c->N2 + kWavesPerBlock - 1) / kWavesPerBlock);
+      const int64_t vn_per = (int64_t)kWavesPerBlock * (64 / W);  // variable nodes per tile
+      b.vn_blocks = (int32_t)((c->N2 + vn_per - 1) / vn_per);
       max_end = std::max(max_end, b.offset + 2 * jb.max_iter);
       for (size_t k = 0; k < cls.size(); ++k) {
         b.cls[k] = cls[k];
@@ -488,7 +495,7 @@ struct Batched {
       for (int k = 0; k < b.n_classes; ++k) {
         const ClassArgs &ck = b.cls[k];
         const int ip = shape_ipw(ck.shape, ipw);
-        const int64_t per = (int64_t)kWavesPerBlock * ip;
+        const int64_t per = (int64_t)kWavesPerBlock * ip * (64 / W);  // checks per tile
         b.cls_blocks[k] = (int32_t)((ck.n_checks + per - 1) / per);
         b.cn_tiles += b.cls_blocks[k];
       }
@@ -507,6 +514,16 @@ struct Batched {
 
   // Everything after the job table copy: set-up, persistent iterations, outputs.
   void enqueue() {
+    if (W == 32)
+      enqueue_w<32>();
+    else if (W == 16)
+      enqueue_w<16>();
+    else
+      enqueue_w<64>();
+  }
+
+  template <int kBatchW>
+  void enqueue_w() {
     for (int j = 0; j < n; ++j) {
       const met_job &jb = jobs[j];
       const met_code *c = jb.code;
@@ -583,7 +600,7 @@ struct Batched {
       tp.B1 = B1 + (size_t)(jb.max_iter & 1) * leaf_words;
       tp.active = reinterpret_cast<uint64_t *>(base + pl.off_active);
       tp.unsat = unsat + (size_t)(jb.max_iter & 1) * G;
-      const int64_t per = kWavesPerBlock;
+      const int64_t per = (int64_t)kWavesPerBlock * (64 / kBatchW);
       hipLaunchKernelGGL(k_test<kBatchW>, dim3((unsigned)((c->M + per - 1) / per), G), dim3(kBlock), 0, st, tp);
       FinalParams fp{};
       fp.vn_slot = d->vn_slot;
@@ -616,6 +633,7 @@ struct Batched {
     (void)hipGetDevice(&dev);
     append_bytes(k, dev);
     append_bytes(k, ipw);
+    append_bytes(k, W);
     append_bytes(k, gen);
     append_bytes(k, grid);
     append_bytes(k, n_phases);
@@ -694,12 +712,19 @@ static int validate_jobs(const met_job *jobs, int32_t n) {
   return MET_OK;
 }
 
+// Enough for every interleave width a launch (or the autotuner) may use.
+static size_t batched_bytes(const met_job *jobs, int32_t n_jobs) {
+  size_t most = 0;
+  for (int w : met::kBatchWidths) most = std::max(most, met::make_batch_layout(jobs, n_jobs, w).total);
+  return most;
+}
+
 extern "C" int met_batched_workspace_bytes(const met_job *jobs, int32_t n_jobs, size_t *bytes) {
   met::clear_error();
   int rc = validate_jobs(jobs, n_jobs);
   if (rc) return rc;
   if (!bytes) return fail(MET_EINVAL, "NULL bytes");
-  *bytes = met::make_batch_layout(jobs, n_jobs).total;
+  *bytes = batched_bytes(jobs, n_jobs);
   return MET_OK;
 }
 
@@ -709,7 +734,7 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
   int rc = validate_jobs(jobs, n_jobs);
   if (rc) return rc;
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(MET_EINVAL, "workspace NULL or not 256-byte aligned");
-  const size_t need = met::make_batch_layout(jobs, n_jobs).total;
+  const size_t need = batched_bytes(jobs, n_jobs);
   if (ws_bytes < need) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   met::Batched b{jobs, n_jobs, static_cast<char *>(workspace), (hipStream_t)stream};
   if (tuning) {
@@ -721,7 +746,10 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
     if (tuning->batch_flags & ~3) return fail(MET_EINVAL, "unknown batch_flags");
     b.stagger = !(tuning->batch_flags & MET_BATCH_NO_STAGGER);
     b.use_graph = !(tuning->batch_flags & MET_BATCH_NO_GRAPH);
-    for (int r = 0; r < 4; ++r)
+    const int w = tuning->interleave;
+    if (w != 0 && w != 16 && w != 32 && w != 64) return fail(MET_EINVAL, "interleave must be 0, 16, 32 or 64");
+    if (w) b.W = w;
+    for (int r = 0; r < 3; ++r)
       if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
   }
   return b.run();
@@ -803,7 +831,7 @@ extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *w
   if (probe_iters < 0 || probe_iters > 1000) return fail(MET_EINVAL, "probe_iters = %d outside 0..1000", probe_iters);
   if (probe_iters == 0) probe_iters = 6;
   if (!workspace || ((uintptr_t)workspace & 255)) return fail(MET_EINVAL, "workspace NULL or not 256-byte aligned");
-  const size_t need = met::make_batch_layout(jobs, n_jobs).total;
+  const size_t need = batched_bytes(jobs, n_jobs);
   if (ws_bytes < need) return fail(MET_EINVAL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   const std::vector<uint8_t> key = met::tune_key(jobs, n_jobs, probe_iters);
   {
@@ -821,10 +849,14 @@ extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *w
   const hipStream_t st = (hipStream_t)stream;
   met_tuning cur{};
   float cur_ms = -1.0f;
-  // steps per wave x resident blocks per CU, then the stagger of the best
-  for (int ipw : {4, 2, 1})
-    for (int bpc : {6, 5, 4, 3, 2}) {
+  // interleave width x steps per wave x resident blocks per CU, then the
+  // stagger of the best (widths below 64 take one step per wave)
+  for (int w : met::kBatchWidths)
+    for (int ipw : {4, 2, 1})
+      for (int bpc : {6, 5, 4, 3, 2}) {
+      if (w != 64 && (ipw != 1 || bpc == 5 || bpc == 3)) continue;
       met_tuning t{};
+      t.interleave = w;
       t.check_steps_per_wave = ipw;
       t.blocks_per_cu = bpc;
       float ms = 0.0f;

@@ -545,7 +545,8 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
     const int u = tuning->variable_chunk;
     if (u != 0 && u != 8 && u != 16 && u != 32) return fail(MET_EINVAL, "variable_chunk must be 0, 8, 16 or 32");
     if (u) chunk = u;
-    for (int r = 0; r < 4; ++r)
+    if (tuning->interleave) return fail(MET_EINVAL, "interleave applies to batched decoding only");
+    for (int r = 0; r < 3; ++r)
       if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
   }
   rc = decode_layout(c, flags, &c);

@@ -56,7 +56,8 @@ def _same(a, b, tag):
 
 
 @pytest.mark.parametrize("tuning", [dict(), dict(check_steps_per_wave=1), dict(check_steps_per_wave=2),
-                                    dict(stagger=False), dict(graph=False), dict(blocks_per_cu=1)])
+                                    dict(stagger=False), dict(graph=False), dict(blocks_per_cu=1),
+                                    dict(interleave=32), dict(interleave=16), dict(interleave=16, graph=False)])
 def test_batched_equals_plain_decode(mix, tuning):
     jobs = [j for j, _ in mix]
     print("batched", tuning, flush=True)
@@ -128,9 +129,11 @@ def test_tree_codes_with_runtime_degree_checks():
         llr = rng.normal(0.5, 1.5, (70, n)).astype(np.float32)
         jobs.append(met.Job(code, torch.from_numpy(llr).to(DEV), torch.from_numpy(s).to(DEV), 25))
     jobs.append(_job("r0.1", 4096, 64, 0.2, 20, 9)[0])
-    out = met.decode_batched(jobs)
-    torch.cuda.synchronize()
-    _same(out, _plain(jobs), "trees")
+    ref = _plain(jobs)
+    for w in (64, 16):
+        out = met.decode_batched(jobs, interleave=w)
+        torch.cuda.synchronize()
+        _same(out, ref, "trees, interleave %d" % w)
 
 
 def test_autotuner_picks_a_valid_shape_and_caches_it(mix):
@@ -143,6 +146,7 @@ def test_autotuner_picks_a_valid_shape_and_caches_it(mix):
     t1 = time.perf_counter()
     print("autotuned", shape, "in %.2f s" % (t1 - t0), flush=True)
     assert shape["check_steps_per_wave"] in (1, 2, 4)
+    assert shape["interleave"] in (16, 32, 64)
     assert 1 <= shape["blocks_per_cu"] <= 6
     assert shape["probe_ms"] > 0
     again = met.BatchedDecoder().autotune(jobs, probe_iters=3)
