@@ -149,6 +149,21 @@ __device__ __forceinline__ T ldro(const T *p, int64_t i) {
   return ((const __attribute__((address_space(4))) T *)p)[i];
 }
 
+// Edge type (scale table row) of edge e.  With 64 frames per item the index is
+// the same in every lane; the byte is then cut from the aligned 32-bit word
+// that holds it, which the scalar unit can fetch (it has no byte loads), so
+// the scale lookup that depends on it stays scalar too.  Every device array
+// of the adjacency is padded to 256 bytes, so the word is inside it.
+template <int W>
+__device__ __forceinline__ int32_t edge_type_of(const int8_t *t, int64_t e) {
+  if constexpr (W == 64) {
+    const uint32_t word = ldro(reinterpret_cast<const uint32_t *>(t), e >> 2);
+    return (int32_t)(int8_t)(uint8_t)(word >> ((uint32_t)(e & 3) * 8u));
+  } else {
+    return ldro(t, e);
+  }
+}
+
 __device__ __forceinline__ float clamp_llr(float x) { return fminf(fmaxf(x, -kLlrMax), kLlrMax); }
 
 __device__ __forceinline__ uint32_t sign_bit(float x) { return __float_as_uint(x) >> 31; }
@@ -333,7 +348,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     for (int m = 0; m < NM; ++m) {
       const float mag = phi(S[m]);
       float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
-      if (weighted) out *= ldro(p.weights, (int64_t)ldro(p.edge_type, m0 + m) * p.wstride + (p.it - 1));
+      if (weighted) out *= ldro(p.weights, (int64_t)edge_type_of<W>(p.edge_type, m0 + m) * p.wstride + (p.it - 1));
       if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
     }
 #pragma unroll
@@ -342,7 +357,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
       const uint32_t neg_l = (neg >> (NM + l)) & 1u;
       const uint32_t neg_c = (tot ^ neg_l) & 1u;
       float wt = 1.0f;
-      if (weighted) wt = ldro(p.weights, (int64_t)ldro(p.leaf_type, le) * p.wstride + (p.it - 1));
+      if (weighted) wt = ldro(p.weights, (int64_t)edge_type_of<W>(p.leaf_type, le) * p.wstride + (p.it - 1));
       uint32_t bit;
       if (wt == 1.0f) {
         bit = leaf_bit(neg_l, neg_c, S[NM + l], A[NM + l]);

@@ -102,14 +102,14 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
       A[k] = phi(fabsf(x));
       neg |= sign_bit(x) << k;
       gsum[k] = p.Pbar[((int64_t)g * p.N2 + vi) * W + w] + p.Cbar[((int64_t)g * p.E12 + e) * W + w];
-      ty[k] = p.edge_type[e];
+      ty[k] = (int8_t)edge_type_of<W>(p.edge_type, e);
     } else if (k < nm + nl) {
       const int64_t le = l0 + (k - nm);
       const float f = p.Lphi[((int64_t)g * p.EL + le) * W + w];
       A[k] = fabsf(f);
       neg |= sign_bit(f) << k;
       gsum[k] = p.gleaf ? p.gleaf[((int64_t)g * p.EL + le) * W + w] : 0.0f;
-      ty[k] = p.leaf_type[le];
+      ty[k] = (int8_t)edge_type_of<W>(p.leaf_type, le);
     }
     if (!valid) gsum[k] = 0.0f;
   }
@@ -168,13 +168,27 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
       if (valid) p.Cbar[((int64_t)g * p.E12 + m0 + k) * W + w] = -vbar;
     }
   }
-  // block sums of dLoss/dw, in a fixed order
+  // block sums of dLoss/dw, in a fixed order.  Wave sums of all types at
+  // once: each of the first three exchange steps hands half of the types
+  // still held to the partner lane and keeps the other half, so after them
+  // lane l holds a partial of type (l >> 3) alone; three more steps finish
+  // its sum (10 exchanges instead of 6 per type).
+  static_assert(kMaxT == 8, "exchange pattern assumes 8 types over 64 lanes");
   __shared__ float red[kWavesPerBlock][kMaxT];
+  {
+    float v4[4], v2[2];
+    const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
 #pragma unroll
-  for (int t = 0; t < kMaxT; ++t) {
-    float v = acc[t];
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) red[threadIdx.x >> 6][t] = v;
+    for (int j = 0; j < 4; ++j)
+      v4[j] = (h32 ? acc[4 + j] : acc[j]) + __shfl_xor(h32 ? acc[j] : acc[4 + j], 32);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      v2[j] = (h16 ? v4[2 + j] : v4[j]) + __shfl_xor(h16 ? v4[j] : v4[2 + j], 16);
+    float v = (h8 ? v2[1] : v2[0]) + __shfl_xor(h8 ? v2[0] : v2[1], 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    if ((lane & 7) == 0) red[threadIdx.x >> 6][lane >> 3] = v;
   }
   __syncthreads();
   if (threadIdx.x < kMaxT) {
