@@ -164,6 +164,33 @@ __device__ __forceinline__ int32_t edge_type_of(const int8_t *t, int64_t e) {
   }
 }
 
+// Scale w[type of the edge, it - 1] of the edge at offset `off` of this lane's
+// item, items being `per` edges apart from `first`.  A wave holds 64 / W
+// consecutive items (lane group q = lane / W has item0 + q); with at most four
+// of them each item's scale is looked up on the scalar unit and the lane picks
+// its own, otherwise every lane loads its type.  Items past n_items (lanes
+// that store nothing) read item 0's.
+template <int W>
+__device__ __forceinline__ float edge_scale(const float *weights, int64_t wstride, int col, const int8_t *types,
+                                            int64_t first, int per, int off, int64_t item0, int64_t n_items, int q,
+                                            int64_t e_lane) {
+  constexpr int IPWAVE = 64 / W;
+  if constexpr (IPWAVE == 1) {
+    return ldro(weights, (int64_t)edge_type_of<64>(types, e_lane) * wstride + col);
+  } else if constexpr (IPWAVE <= 4) {
+    float r = 0.0f;
+#pragma unroll
+    for (int u = 0; u < IPWAVE; ++u) {
+      const int64_t iu = item0 + u < n_items ? item0 + u : 0;
+      const float wu = ldro(weights, (int64_t)edge_type_of<64>(types, first + iu * per + off) * wstride + col);
+      r = (q == u) ? wu : r;
+    }
+    return r;
+  } else {
+    return ldro(weights, (int64_t)ldro(types, e_lane) * wstride + col);
+  }
+}
+
 __device__ __forceinline__ float clamp_llr(float x) { return fminf(fmaxf(x, -kLlrMax), kLlrMax); }
 
 __device__ __forceinline__ uint32_t sign_bit(float x) { return __float_as_uint(x) >> 31; }
@@ -348,7 +375,9 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     for (int m = 0; m < NM; ++m) {
       const float mag = phi(S[m]);
       float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
-      if (weighted) out *= ldro(p.weights, (int64_t)edge_type_of<W>(p.edge_type, m0 + m) * p.wstride + (p.it - 1));
+      if (weighted)
+        out *= edge_scale<W>(p.weights, p.wstride, p.it - 1, p.edge_type, c.first_msg, NM, m, base + k * IPWAVE,
+                             c.n_checks, q, m0 + m);
       if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
     }
 #pragma unroll
@@ -357,7 +386,9 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
       const uint32_t neg_l = (neg >> (NM + l)) & 1u;
       const uint32_t neg_c = (tot ^ neg_l) & 1u;
       float wt = 1.0f;
-      if (weighted) wt = ldro(p.weights, (int64_t)edge_type_of<W>(p.leaf_type, le) * p.wstride + (p.it - 1));
+      if (weighted)
+        wt = edge_scale<W>(p.weights, p.wstride, p.it - 1, p.leaf_type, c.first_leaf, NL, l, base + k * IPWAVE,
+                           c.n_checks, q, le);
       uint32_t bit;
       if (wt == 1.0f) {
         bit = leaf_bit(neg_l, neg_c, S[NM + l], A[NM + l]);
