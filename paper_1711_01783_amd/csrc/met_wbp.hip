@@ -230,8 +230,32 @@ __global__ __launch_bounds__(kBlock) void k_variable_adj(const VarAdjParams p) {
   const int64_t i = ((int64_t)blockIdx.x * kWavesPerBlock + wave_id()) * (64 / W) + q;
   if (i >= p.N2) return;
   const float *cb = p.Cbar + (int64_t)g * p.E12 * W + w;
+  const int32_t e1 = ldro(p.vn_ptr, i + 1);
+  int32_t e = ldro(p.vn_ptr, i);
   float s = 0.0f;
-  for (int32_t e = ldro(p.vn_ptr, i); e < ldro(p.vn_ptr, i + 1); ++e) s += cb[(int64_t)ldro(p.vn_edges, e) * W];
+  // gathers issued in batches, summed in edge order
+  for (; e + 8 <= e1; e += 8) {
+    float a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = cb[(int64_t)ldro(p.vn_edges, e + u) * W];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += a[u];
+  }
+  if (e + 4 <= e1) {
+    float a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = cb[(int64_t)ldro(p.vn_edges, e + u) * W];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += a[u];
+    e += 4;
+  }
+  if (e + 2 <= e1) {
+    const float a0 = cb[(int64_t)ldro(p.vn_edges, e) * W], a1 = cb[(int64_t)ldro(p.vn_edges, e + 1) * W];
+    s += a0;
+    s += a1;
+    e += 2;
+  }
+  if (e < e1) s += cb[(int64_t)ldro(p.vn_edges, e) * W];
   p.Pbar[((int64_t)g * p.N2 + i) * W + w] = -s;
 }
 
