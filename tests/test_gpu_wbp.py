@@ -39,7 +39,7 @@ def _loss_grad_gpu(code_g, llr, syn, bits, w, k):
     loss = torch.nn.functional.softplus(-s * post).mean()
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), wt.grad.cpu().numpy(), post.detach().cpu().numpy()
+    return float(loss.detach()), wt.grad.cpu().numpy(), post.detach().cpu().numpy()
 
 
 def test_unit_weights_bit_identical_to_plain_decode():
@@ -53,8 +53,12 @@ def test_unit_weights_bit_identical_to_plain_decode():
     np.testing.assert_array_equal(c1.cpu().numpy(), out.converged.cpu().numpy())
 
 
+# frame counts 8 and 5 run in groups of 16 frames (four checks per wave), 1 in
+# groups of one, 24 in groups of 32 (two checks per wave) and 40 in groups of
+# 64 (one check per wave); odd lengths leave a partly filled last wave
 @pytest.mark.parametrize("prof,n,b,snr,it", [("r0.1", 4096, 8, 0.2, 10), ("r0.02", 4096, 5, 0.07, 8),
-                                             ("r0.05", 3000, 1, 0.12, 6)])
+                                             ("r0.05", 3000, 1, 0.12, 6), ("r0.1", 2010, 24, 0.2, 6),
+                                             ("r0.02", 2550, 40, 0.07, 5)])
 def test_forward_and_gradient_match_fp64_oracle(prof, n, b, snr, it):
     code_o, code_g, bits, llr, syn = _case(prof, n, b, snr)
     rng = np.random.default_rng(1)
