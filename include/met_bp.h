@@ -79,6 +79,7 @@ extern "C" {
 
 #define MET_MAX_EDGE_TYPES 8
 #define MET_MAX_CHECK_DEGREE 32
+#define MET_MAX_VN_DEGREE 65536
 
 typedef struct met_code met_code; /* opaque */
 
@@ -118,10 +119,13 @@ typedef struct {
  * variable/check pair repeats, then sorted by (check, edge type, variable).
  * The paper uses progressive edge growth instead (Methods, first paragraph);
  * this construction is the project's substitute.  Host-only: needs no GPU.
- * p: host profile; N >= 2; *out receives a new handle.
+ * p: host profile; 2 <= N <= 2^30; *out receives a new handle.
  * Errors: MET_EINVAL for an inconsistent profile (edge type in two check types,
- * unbalanceable sockets, check degree < 2 or > MET_MAX_CHECK_DEGREE, failed
- * multi-edge repair), MET_ENOMEM. */
+ * unbalanceable sockets, check degree < 2 or > MET_MAX_CHECK_DEGREE, variable
+ * degree above MET_MAX_VN_DEGREE, failed multi-edge repair) or more than
+ * INT32_MAX edges (edge positions are int32), MET_ENOMEM when host memory runs
+ * out.  No entry point lets a C++ exception escape: an unexpected one returns
+ * MET_ESTATE with its message in met_last_error(). */
 int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out);
 
 /* A code from an explicit edge list (E edges, host arrays, any order; etype may

@@ -719,17 +719,18 @@ static size_t batched_bytes(const met_job *jobs, int32_t n_jobs) {
   return most;
 }
 
-extern "C" int met_batched_workspace_bytes(const met_job *jobs, int32_t n_jobs, size_t *bytes) {
+extern "C" int met_batched_workspace_bytes(const met_job *jobs, int32_t n_jobs, size_t *bytes) { return met::guarded("met_batched_workspace_bytes", [&]() -> int {
   met::clear_error();
   int rc = validate_jobs(jobs, n_jobs);
   if (rc) return rc;
   if (!bytes) return fail(MET_EINVAL, "NULL bytes");
   *bytes = batched_bytes(jobs, n_jobs);
   return MET_OK;
+  });
 }
 
 extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
-                                  const met_tuning *tuning, void *stream) {
+                                  const met_tuning *tuning, void *stream) { return met::guarded("met_decode_batched", [&]() -> int {
   met::clear_error();
   int rc = validate_jobs(jobs, n_jobs);
   if (rc) return rc;
@@ -753,6 +754,7 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
       if (tuning->reserved[r]) return fail(MET_EINVAL, "reserved tuning fields must be 0");
   }
   return b.run();
+  });
 }
 
 // ---- Autotuning -------------------------------------------------------------
@@ -823,7 +825,7 @@ int time_shape(const std::vector<met_job> &probe, char *ws, hipStream_t st, cons
 }  // namespace met
 
 extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *workspace, size_t ws_bytes,
-                                    int32_t probe_iters, met_tuning *best, float *best_ms, void *stream) {
+                                    int32_t probe_iters, met_tuning *best, float *best_ms, void *stream) { return met::guarded("met_batched_autotune", [&]() -> int {
   met::clear_error();
   int rc = validate_jobs(jobs, n_jobs);
   if (rc) return rc;
@@ -886,9 +888,10 @@ extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *w
   *best = cur;
   if (best_ms) *best_ms = cur_ms;
   return MET_OK;
+  });
 }
 
-extern "C" int met_batched_check(const void *workspace, int32_t *barrier_expired) {
+extern "C" int met_batched_check(const void *workspace, int32_t *barrier_expired) { return met::guarded("met_batched_check", [&]() -> int {
   met::clear_error();
   if (!workspace || !barrier_expired) return fail(MET_EINVAL, "NULL argument");
   met::BarrierState s{};
@@ -896,4 +899,5 @@ extern "C" int met_batched_check(const void *workspace, int32_t *barrier_expired
   if (e != hipSuccess) return fail(MET_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
   *barrier_expired = s.err;
   return MET_OK;
+  });
 }

@@ -293,7 +293,7 @@ static int sort_and_finalize(met_code *c, std::vector<int32_t> &v, std::vector<i
   return met::finalize_code(c);
 }
 
-extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out) {
+extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out) { return met::guarded("met_code_build", [&]() -> int {
   met::clear_error();
   if (!p || !out) return fail(MET_EINVAL, "met_code_build: NULL argument");
   *out = nullptr;
@@ -304,7 +304,8 @@ extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, me
   if (N < 2 || N > ((int64_t)1 << 30)) return fail(MET_EINVAL, "N = %lld outside 2..2^30", (long long)N);
   const int VT = p->n_vn_types, CT = p->n_cn_types;
   for (int k = 0; k < VT * T; ++k)
-    if (p->vn_deg[k] < 0) return fail(MET_EINVAL, "negative VN degree");
+    if (p->vn_deg[k] < 0 || p->vn_deg[k] > MET_MAX_VN_DEGREE)
+      return fail(MET_EINVAL, "VN degree %d outside 0..%d", p->vn_deg[k], MET_MAX_VN_DEGREE);
   for (int k = 0; k < CT * T; ++k)
     if (p->cn_deg[k] < 0) return fail(MET_EINVAL, "negative check degree");
   // 1. VN counts
@@ -326,10 +327,15 @@ extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, me
     for (int t = 0; t < T; ++t) dsum += p->vn_deg[k * T + t];
     if (vcount[k] > 0 && dsum < 1) return fail(MET_EINVAL, "VN type %d has degree 0", k);
   }
-  // 2. sockets per type
+  // 2. sockets per type; every edge position is an int32 index
   std::vector<int64_t> S(T, 0);
-  for (int t = 0; t < T; ++t)
+  int64_t E_total = 0;
+  for (int t = 0; t < T; ++t) {
     for (int k = 0; k < VT; ++k) S[t] += vcount[k] * p->vn_deg[k * T + t];
+    E_total += S[t];
+  }
+  if (E_total > (int64_t)INT32_MAX)
+    return fail(MET_EINVAL, "%lld edges exceed the int32 edge index", (long long)E_total);
   // 3. check counts
   std::vector<int> owner(T, -1);
   for (int k = 0; k < CT; ++k)
@@ -471,10 +477,11 @@ extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, me
   }
   *out = code;
   return MET_OK;
+  });
 }
 
 extern "C" int met_code_from_edges(int64_t N, int64_t M, int64_t E, const int32_t *vn, const int32_t *cn,
-                                   const int8_t *etype, met_code **out) {
+                                   const int8_t *etype, met_code **out) { return met::guarded("met_code_from_edges", [&]() -> int {
   met::clear_error();
   if (!out || !vn || !cn) return fail(MET_EINVAL, "met_code_from_edges: NULL argument");
   *out = nullptr;
@@ -512,9 +519,10 @@ extern "C" int met_code_from_edges(int64_t N, int64_t M, int64_t E, const int32_
   }
   *out = code;
   return MET_OK;
+  });
 }
 
-extern "C" int met_code_info(const met_code *c, met_code_stats *o) {
+extern "C" int met_code_info(const met_code *c, met_code_stats *o) { return met::guarded("met_code_info", [&]() -> int {
   met::clear_error();
   if (!c || !o) return fail(MET_EINVAL, "met_code_info: NULL argument");
   std::memset(o, 0, sizeof *o);
@@ -532,18 +540,20 @@ extern "C" int met_code_info(const met_code *c, met_code_stats *o) {
   o->max_check_degree = c->max_check_deg;
   o->max_vn_degree = c->max_vn_deg;
   return MET_OK;
+  });
 }
 
-extern "C" int met_code_export(const met_code *c, int32_t *vn, int32_t *cn, int8_t *etype) {
+extern "C" int met_code_export(const met_code *c, int32_t *vn, int32_t *cn, int8_t *etype) { return met::guarded("met_code_export", [&]() -> int {
   met::clear_error();
   if (!c) return fail(MET_EINVAL, "met_code_export: NULL code");
   if (vn) std::memcpy(vn, c->vn.data(), c->E * sizeof(int32_t));
   if (cn) std::memcpy(cn, c->cn.data(), c->E * sizeof(int32_t));
   if (etype) std::memcpy(etype, c->et.data(), c->E * sizeof(int8_t));
   return MET_OK;
+  });
 }
 
-extern "C" int met_code_classes(const met_code *c, met_check_class *out, int32_t max_entries, int32_t *n) {
+extern "C" int met_code_classes(const met_code *c, met_check_class *out, int32_t max_entries, int32_t *n) { return met::guarded("met_code_classes", [&]() -> int {
   met::clear_error();
   if (!c || !out || !n || max_entries < 0) return fail(MET_EINVAL, "met_code_classes: NULL argument");
   const int32_t k = std::min<int32_t>(max_entries, (int32_t)c->classes.size());
@@ -566,4 +576,5 @@ extern "C" int met_code_classes(const met_code *c, met_check_class *out, int32_t
   }
   *n = (int32_t)c->classes.size();
   return MET_OK;
+  });
 }

@@ -481,7 +481,7 @@ extern "C" void met_code_free(met_code *c) {
   delete c;
 }
 
-extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, uint8_t *syn, void *stream) {
+extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, uint8_t *syn, void *stream) { return met::guarded("met_syndrome", [&]() -> int {
   met::clear_error();
   if (!c || !bits || !syn) return fail(MET_EINVAL, "met_syndrome: NULL argument");
   if (B < 1 || B > 65535) return fail(MET_EINVAL, "met_syndrome: B = %d outside 1..65535", B);
@@ -492,6 +492,7 @@ extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, u
                      dim3(met::kBlock), 0, (hipStream_t)stream, d->all_vn, d->all_ptr, c->N, c->M, bits, syn);
   HIP_TRY(hipGetLastError());
   return MET_OK;
+  });
 }
 
 static int validate_decode(const met_code *c, int32_t B, uint32_t flags) {
@@ -515,7 +516,7 @@ static int decode_layout(const met_code *c, uint32_t flags, const met_code **out
 }
 
 extern "C" int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int32_t want_posterior,
-                                          size_t *bytes) {
+                                          size_t *bytes) { return met::guarded("met_decode_workspace_bytes", [&]() -> int {
   met::clear_error();
   int rc = validate_decode(c, B, flags);
   if (rc) return rc;
@@ -524,11 +525,12 @@ extern "C" int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t
   if (rc) return rc;
   *bytes = met::make_plan(c, B, want_posterior != 0, false, met::choose_interleave(B), c2v_bytes(flags)).total;
   return MET_OK;
+  });
 }
 
 extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
                              uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
-                             void *workspace, size_t ws_bytes, const met_tuning *tuning, void *stream) {
+                             void *workspace, size_t ws_bytes, const met_tuning *tuning, void *stream) { return met::guarded("met_decode_ex", [&]() -> int {
   met::clear_error();
   int rc = validate_decode(c, B, flags);
   if (rc) return rc;
@@ -567,23 +569,26 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
     case 32: return dec.run<32>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
     default: return dec.run<64>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   }
+  });
 }
 
 extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
                           uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
-                          void *workspace, size_t ws_bytes, void *stream) {
+                          void *workspace, size_t ws_bytes, void *stream) { return met::guarded("met_decode", [&]() -> int {
   return met_decode_ex(c, llr, syn, B, max_iter, flags, bits, iters, converged, posterior, workspace, ws_bytes,
                        nullptr, stream);
+  });
 }
 
-extern "C" int met_timing_enable(int32_t on) {
+extern "C" int met_timing_enable(int32_t on) { return met::guarded("met_timing_enable", [&]() -> int {
   met::clear_error();
   std::lock_guard<std::mutex> lock(met::g_timing.mu);
   met::g_timing.on = on != 0;
   return MET_OK;
+  });
 }
 
-extern "C" int met_timing_collect(met_kernel_time *out, int32_t max_entries, int32_t *n_entries) {
+extern "C" int met_timing_collect(met_kernel_time *out, int32_t max_entries, int32_t *n_entries) { return met::guarded("met_timing_collect", [&]() -> int {
   met::clear_error();
   if (!out || !n_entries || max_entries < 0) return fail(MET_EINVAL, "met_timing_collect: bad output");
   std::vector<met::TimingState::Rec> recs;
@@ -618,4 +623,5 @@ extern "C" int met_timing_collect(met_kernel_time *out, int32_t max_entries, int
   }
   *n_entries = n;
   return rc;
+  });
 }

@@ -2,7 +2,9 @@
 #pragma once
 
 #include <cstdint>
+#include <exception>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -13,6 +15,22 @@ namespace met {
 // Records a message for met_last_error() and returns `code`.
 int fail(int code, const char *fmt, ...);
 void clear_error();
+
+// Runs the body of a C-ABI entry point: a C++ exception (above all a failed
+// allocation of a host container) becomes an error code and a message for
+// met_last_error() instead of crossing the C boundary.
+template <class F>
+int guarded(const char *name, F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return fail(MET_ENOMEM, "%s: out of host memory", name);
+  } catch (const std::exception &e) {
+    return fail(MET_ESTATE, "%s: %s", name, e.what());
+  } catch (...) {
+    return fail(MET_ESTATE, "%s: unexpected exception", name);
+  }
+}
 
 // Check shapes with a compiled kernel path: (message edges, leaf edges) per
 // check.  "Message" edges go to variable nodes of degree >= 2; "leaf" edges go

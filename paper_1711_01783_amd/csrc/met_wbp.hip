@@ -674,13 +674,14 @@ int validate_wbp(const met_code *c, int32_t B, int32_t L, int32_t k) {
 using met::fail;
 
 extern "C" int met_wbp_workspace_bytes(const met_code *c, int32_t B, int32_t iterations, int32_t ckpt_every,
-                                       size_t *bytes) {
+                                       size_t *bytes) { return met::guarded("met_wbp_workspace_bytes", [&]() -> int {
   met::clear_error();
   int rc = met::validate_wbp(c, B, iterations, ckpt_every);
   if (rc) return rc;
   if (!bytes) return fail(MET_EINVAL, "NULL bytes");
   *bytes = met::make_wbp_plan(c, B, iterations, ckpt_every).total;
   return MET_OK;
+  });
 }
 
 static int wbp_common(const met_code *c, int32_t B, int32_t L, int32_t k, const float *weights, void *ws,
@@ -697,7 +698,7 @@ static int wbp_common(const met_code *c, int32_t B, int32_t L, int32_t k, const 
 
 extern "C" int met_wbp_forward(const met_code *c, const float *llr, const uint8_t *syn, int32_t B,
                                int32_t iterations, const float *weights, int32_t ckpt_every, float *posterior,
-                               uint8_t *bits, uint8_t *converged, void *workspace, size_t ws_bytes, void *stream) {
+                               uint8_t *bits, uint8_t *converged, void *workspace, size_t ws_bytes, void *stream) { return met::guarded("met_wbp_forward", [&]() -> int {
   met::clear_error();
   if (!llr || !syn || !posterior) return fail(MET_EINVAL, "NULL buffer");
   if (((uintptr_t)llr & 3) || ((uintptr_t)posterior & 3)) return fail(MET_EINVAL, "misaligned float buffer");
@@ -713,11 +714,12 @@ extern "C" int met_wbp_forward(const met_code *c, const float *llr, const uint8_
     case 32: return w.forward<32>(llr, syn, posterior, bits, converged);
     default: return w.forward<64>(llr, syn, posterior, bits, converged);
   }
+  });
 }
 
 extern "C" int met_wbp_backward(const met_code *c, const float *grad_posterior, int32_t B, int32_t iterations,
                                 const float *weights, int32_t ckpt_every, float *grad_weights, void *workspace,
-                                size_t ws_bytes, void *stream) {
+                                size_t ws_bytes, void *stream) { return met::guarded("met_wbp_backward", [&]() -> int {
   met::clear_error();
   if (!grad_posterior || !grad_weights) return fail(MET_EINVAL, "NULL buffer");
   if (((uintptr_t)grad_posterior & 3) || ((uintptr_t)grad_weights & 3)) return fail(MET_EINVAL, "misaligned buffer");
@@ -733,4 +735,5 @@ extern "C" int met_wbp_backward(const met_code *c, const float *grad_posterior, 
     case 32: return w.backward<32>(grad_posterior, grad_weights);
     default: return w.backward<64>(grad_posterior, grad_weights);
   }
+  });
 }

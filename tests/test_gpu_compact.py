@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_1711_01783_amd as met  # noqa: E402
 from met_inputs import PROFILES, make_frames  # noqa: E402
+from oracle import bp, code as oc  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -50,6 +51,16 @@ def test_compaction_changes_nothing_at_waterfall(prof, n, b, snr, max_iter):
     it, conv = on[1], on[2]
     # a spread of exit iterations, so that compaction points saw partial groups
     assert 0.2 < conv.mean() < 0.98 and np.unique(it[conv == 1]).size > 5
+    # 16 frames spread over the groups against the FP64 oracle: identical bits
+    # where both converged, counts within one, and every converged flag equal
+    # to the exact syndrome test of the decoded bits
+    code_o = oc.build(PROFILES[prof], n, 21)
+    pick = np.linspace(0, b - 1, 16).astype(int)
+    ref = bp.decode(code_o, llr[pick], oc.syndrome(code_o, bits[pick]), max_iter)
+    both = (conv[pick] == 1) & (ref.converged == 1)
+    np.testing.assert_array_equal(on[0][pick][both], ref.bits[both])
+    assert np.all(np.abs(it[pick][both].astype(int) - ref.iterations[both]) <= 1)
+    np.testing.assert_array_equal(conv, np.all(oc.syndrome(code_o, on[0]) == syn.cpu().numpy(), axis=1))
 
 
 def test_forced_moves_between_groups():

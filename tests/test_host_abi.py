@@ -102,6 +102,18 @@ def test_profile_validation():
         met.Code.build(PROFILES["r0.1"], 1, 1)
 
 
+def test_edge_count_limited_to_int32_before_allocating():
+    """Edge positions are int32: a code with more than 2^31 - 1 edges (the
+    rate-0.1 profile at N = 2^30 has about 4.0e9) is refused before any socket
+    list is built, and so is a variable degree past the documented bound."""
+    with pytest.raises(met.MetError, match="exceed the int32 edge index") as e:
+        met.Code.build(PROFILES["r0.1"], 2 ** 30, 1)
+    assert e.value.code == -1
+    huge = Profile("huge", 0.5, vn_types=((0.5, (70000, 0)), (0.5, (0, 1))), cn_types=((0.5, (0, 1)),))
+    with pytest.raises(met.MetError, match="VN degree"):
+        met.Code.build(huge, 100, 1)
+
+
 def test_decode_argument_validation_without_gpu():
     """Validation happens before any HIP call, so it works on a GPU-less host."""
     c = met.Code.build(PROFILES["r0.1"], 4096, 1)

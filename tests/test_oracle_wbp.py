@@ -65,3 +65,36 @@ def test_posteriors_are_affine_in_last_iteration_weights():
     p0 = wbp.posteriors(code, llr, syn, w0, it)
     np.testing.assert_allclose(p0, llr.astype(np.float64), atol=0)
     np.testing.assert_allclose(p2 - p0, 2 * (p1 - p0), rtol=1e-12, atol=1e-12)
+
+
+def test_bce_loss_closed_forms():
+    """The loss against the binary cross-entropy written with probabilities.
+
+    With L = ln p(0)/p(1) (the LLR sign convention of eq. (1), read as a ratio
+    of bit probabilities), a posterior P means p(bit = 1) = 1 / (1 + e^P), and
+    the cross-entropy of a sent bit x is -ln p(x).  P = ln 3 gives
+    p(1) = 1/4: cost ln(4/3) for a sent 0 and ln 4 for a sent 1; P = 0 costs
+    ln 2 either way.  A swapped sign convention would exchange the first two.
+    """
+    post = torch.tensor([[np.log(3.0), np.log(3.0)], [0.0, 0.0]], dtype=torch.float64)
+    bits = np.array([[0, 1], [0, 1]], dtype=np.uint8)
+    per_bit = [np.log(4.0 / 3.0), np.log(4.0), np.log(2.0), np.log(2.0)]
+    assert abs(float(wbp.bce_loss(post, bits)) - np.mean(per_bit)) <= 1e-15
+    # one element at a time, against -ln p(x) with p from the posterior ratio
+    rng = np.random.default_rng(5)
+    p = rng.normal(0.0, 4.0, (3, 7))
+    x = rng.integers(0, 2, (3, 7)).astype(np.uint8)
+    p1 = 1.0 / (1.0 + np.exp(p))
+    direct = -np.mean(np.where(x == 1, np.log(p1), np.log1p(-p1)))
+    assert abs(float(wbp.bce_loss(torch.as_tensor(p), x)) - direct) <= 1e-13
+
+
+def test_bce_loss_gradient_is_probability_minus_bit():
+    """d(-ln p(x))/dP = x - p(1): the gradient the adjoint sweep starts from,
+    divided by the number of bits averaged."""
+    rng = np.random.default_rng(6)
+    p = torch.tensor(rng.normal(0.0, 3.0, (2, 5)), requires_grad=True)
+    x = rng.integers(0, 2, (2, 5)).astype(np.uint8)
+    wbp.bce_loss(p, x).backward()
+    p1 = 1.0 / (1.0 + np.exp(p.detach().numpy()))
+    np.testing.assert_allclose(p.grad.numpy(), (x - p1) / x.size, rtol=1e-12, atol=1e-15)
