@@ -179,3 +179,38 @@ def test_graph_cache_does_not_outlive_a_freed_code():
         torch.cuda.synchronize()
         _same(outs, _plain([job]), "seed %d" % seed)
         code.close()
+
+
+def test_batched_against_the_oracle_at_waterfall_snrs():
+    """One persistent launch of three jobs (one per rate, waterfall SNRs, budgets
+    60 / 90 / 120) against the FP64 oracle directly: converged flags are the
+    exact syndrome test of the decoded bits, and every frame's word, flag and
+    count (within one iteration) equal the oracle's, except frames on which the
+    oracle's own outcome moves under 1e-7 perturbations of the inputs (listed)."""
+    from oracle import code as oc
+    from tests import oracle_outcome as oo
+
+    specs = [("r0.1", 16384, 40, 0.19, 60, 41), ("r0.05", 12000, 33, 0.10, 90, 42),
+             ("r0.02", 9000, 24, 0.065, 120, 43)]
+    jobs, inputs = [], []
+    for prof, n, b, snr, max_iter, seed in specs:
+        code = met.Code.build(PROFILES[prof], n, seed)
+        bits, llr = make_frames(n, b, snr, 700 + seed)
+        code_o = oc.build(PROFILES[prof], n, seed)
+        syn = oc.syndrome(code_o, bits)
+        jobs.append(met.Job(code, torch.from_numpy(llr).to(DEV), torch.from_numpy(syn).to(DEV), max_iter))
+        inputs.append((code_o, llr, syn, max_iter))
+    print("batched vs oracle", [s[:5] for s in specs], flush=True)
+    dec = met.BatchedDecoder()
+    out = dec(jobs)
+    torch.cuda.synchronize()
+    assert not dec.barrier_expired()
+    for (code_o, llr, syn, max_iter), o, spec in zip(inputs, out, specs):
+        got = o.bits.cpu().numpy(), o.converged.cpu().numpy(), o.iterations.cpu().numpy()
+        acc, rep = oo.compare(code_o, llr, syn, max_iter, *got)
+        print("  %s: %d of %d frames converged, %d differ from the oracle with proof" % (
+            spec[0], int(got[1].sum()), spec[2], len(acc)), flush=True)
+        for line in rep:
+            print("   ", line, flush=True)
+        assert got[1].sum() >= spec[2] // 4
+        assert len(acc) <= spec[2] // 10
