@@ -41,6 +41,7 @@ __all__ = [
     "channel_llr",
     "make_frames",
     "beta_efficiency",
+    "gaussian_raw_keys",
 ]
 
 
@@ -136,3 +137,26 @@ def make_frames(n: int, frames: int, snr: float, seed: int, first_frame: int = 0
     bits = frame_bits(n, frames, seed, first_frame)
     llr = channel_llr(bits, snr, seed, first_frame)
     return bits, llr
+
+
+def gaussian_raw_keys(n: int, frames: int, snr: float, seed: int, first_frame: int = 0):
+    """Correlated Gaussian raw keys of a CV-QKD run and Bob's random string.
+
+    Returns (x, y, u): x float32 [frames, n] Alice's variables, X ~ N(0, SNR)
+    (unit noise, so that SNR = sigma_X^2 / sigma_Z^2); y float32 Bob's,
+    Y = X + Z with Z ~ N(0, 1) (Results, "Information reconciliation for CV-QKD
+    system"); u uint8 [frames, n] the uniform bits Bob maps his variables onto.
+    Frame f draws x, then z, then u from PCG64(seed + f), in that order.
+    """
+    x = np.empty((frames, n), dtype=np.float32)
+    y = np.empty((frames, n), dtype=np.float32)
+    u = np.empty((frames, n), dtype=np.uint8)
+    sx = math.sqrt(snr)
+    for i in range(frames):
+        g = _rng(seed, first_frame + i)
+        xf = sx * g.standard_normal(n)
+        zf = g.standard_normal(n)
+        x[i] = xf.astype(np.float32)
+        y[i] = (xf + zf).astype(np.float32)
+        u[i] = g.integers(0, 2, size=n, dtype=np.uint8)
+    return x, y, u

@@ -15,6 +15,9 @@ bp        flooding belief propagation in the LLR domain, FP64, following the
 map       exhaustive maximum-a-posteriori decoding for tiny codes (pin for bp).
 wbp       weighted BP (learnable scale per edge type and iteration on
           check-to-variable messages) with an FP64 reverse-mode gradient.
+mdr       multidimensional reconciliation (the decoder's front end): Bob's
+          rotation coefficients and Alice's virtual-channel LLRs from Gaussian
+          raw keys, with explicit Cayley-Dickson multiplication matrices.
 
 Every function is pinned by tests under ``tests/`` against something other than
 itself (brute-force MAP on tree codes, closed-form boxplus, invariants, the
