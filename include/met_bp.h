@@ -128,6 +128,27 @@ typedef struct {
  * MET_ESTATE with its message in met_last_error(). */
 int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out);
 
+/* Builds a code from a degree profile by progressive edge growth, the
+ * construction the paper uses (Methods, first paragraph).  Node counts and
+ * per-check socket counts as in met_code_build; then edges are placed node by
+ * node (v = 0..N-1), edge type by edge type, each to the check that is, among
+ * those with a free socket of its type and not yet adjacent to v, outside the
+ * deepest breadth-first layer of v's neighbourhood in the type-t graph built
+ * so far (at most depth[t] check layers searched), among those the least
+ * filled with type-t edges, and among ties a seeded uniform draw (SplitMix64
+ * stream number n_edge_types, one draw per edge).  No cycle of length
+ * <= 2 depth[t] enters the type-t graph wherever free sockets allow; no pair
+ * repeats.
+ * depth: host int32 [n_edge_types], each 1..16, or NULL for the default
+ * (1 where a layer cannot grow, else the largest K with
+ * (d_v - 1) ((d_v - 1)(d_c - 1))^(K-1) <= 1024 for the largest type-t degrees
+ * d_v, d_c: the expected size of the last layer searched).
+ * Cost grows with the searched layers: N = 10^6 at the default depths takes
+ * seconds to tens of seconds on one host core.
+ * Errors: as met_code_build, and MET_EINVAL for a depth outside 1..16 or an
+ * edge that finds no free check. */
+int met_code_build_peg(const met_profile *p, int64_t N, uint64_t seed, const int32_t *depth, met_code **out);
+
 /* A code from an explicit edge list (E edges, host arrays, any order; etype may
  * be NULL for a single edge type).  Used for small hand-built codes in tests.
  * Errors: MET_EINVAL for out-of-range indices, repeated pairs, a check of
@@ -169,6 +190,35 @@ void met_code_free(met_code *c);
  * The first call on a device uploads the adjacency (allocates device memory).
  * Errors: MET_EINVAL (NULL pointer, B < 1), MET_EHIP. */
 int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, uint8_t *syn, void *stream);
+
+/* ---- Multidimensional reconciliation (the decoder's front end) ----------
+ * Results, "Information reconciliation for CV-QKD system", and Methods Step 1:
+ * the correlated Gaussian raw keys of Alice (x) and Bob (y = x + z, noise
+ * variance sigma_z^2) become Bob's random bit string and, on Alice's side,
+ * log-likelihood ratios of a virtual binary-input AWGN channel, which
+ * met_decode takes together with Bob's syndrome (met_syndrome of his bits).
+ * Both strings are cut into blocks of d in {1, 2, 4, 8} consecutive values of a
+ * frame, read as elements of the Cayley-Dickson algebra of dimension d
+ * (product (a, b)(c, e) = (a c - conj(e) b, e a + b conj(c)), conj((a, b)) =
+ * (conj(a), -b): reals, complex numbers, quaternions, octonions).
+ *
+ * Bob: for each block, alpha = u conj(y / |y|) with u = (1 - 2 bits) / sqrt(d)
+ * (y / |y| taken as e_0 when |y| = 0), so that alpha (y / |y|) = u.
+ *   y:     dev float32 [B][N], 16-byte aligned
+ *   bits:  dev uint8   [B][N] (0/1; only bit 0 is read), 8-byte aligned
+ *   alpha: dev float32 [B][N] output (one unit element per block), 16-byte aligned
+ *   ynorm: dev float32 [B][N/d] output, |y| of every block
+ * Alice: llr = 2 |y| (alpha x) / (sqrt(d) sigma_z^2) per block, i.e.
+ * 2 |x| |y| v / (sqrt(d) sigma_z^2) with v = alpha x / |x| her noisy copy of u;
+ * L = ln p(bit 0) / p(bit 1), the decoder's convention.
+ *   x, alpha: dev float32 [B][N], ynorm dev float32 [B][N/d]; llr dev float32
+ *   [B][N] output; x, alpha, llr 16-byte aligned; sigma_z2 > 0.
+ * N must be a multiple of d and B N <= 2^36.  The caller owns every buffer;
+ * work is queued on the stream.  Errors: MET_EINVAL, MET_EHIP. */
+int met_mdr_bob(const float *y, const uint8_t *bits, int64_t B, int64_t N, int32_t d, float *alpha, float *ynorm,
+                void *stream);
+int met_mdr_alice(const float *x, const float *alpha, const float *ynorm, float sigma_z2, int64_t B, int64_t N,
+                  int32_t d, float *llr, void *stream);
 
 /* Workspace size in bytes that met_decode needs for this code, B frames and
  * these flags (want_posterior != 0 when a posterior output will be passed).

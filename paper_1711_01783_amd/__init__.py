@@ -17,7 +17,8 @@ from ._lib import (
     lib,
     library_path,
 )
-from .api import (BatchedDecoder, Code, DecodeOutput, Job, batched_workspace_bytes, decode, decode_batched, syndrome,
+from .api import (BatchedDecoder, Code, DecodeOutput, Job, batched_workspace_bytes, decode, decode_batched, mdr_alice, mdr_bob,
+                  syndrome,
                   timing_collect, timing_enable, workspace_bytes)
 
 __all__ = [
@@ -27,6 +28,8 @@ __all__ = [
     "Job",
     "batched_workspace_bytes",
     "decode_batched",
+    "mdr_alice",
+    "mdr_bob",
     "MET_EARLY_EXIT",
     "MET_FIXED_ITERS",
     "MetError",

@@ -94,6 +94,7 @@ def _load():
     i32, i64, u32, u64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
     sig = {
         "met_code_build": (ctypes.c_int, [ctypes.POINTER(met_profile), i64, u64, ctypes.POINTER(P)]),
+        "met_code_build_peg": (ctypes.c_int, [ctypes.POINTER(met_profile), i64, u64, P, ctypes.POINTER(P)]),
         "met_code_from_edges": (ctypes.c_int, [i64, i64, i64, P, P, P, ctypes.POINTER(P)]),
         "met_code_info": (ctypes.c_int, [P, ctypes.POINTER(met_code_stats)]),
         "met_code_export": (ctypes.c_int, [P, P, P, P]),
@@ -102,6 +103,8 @@ def _load():
         "met_syndrome": (ctypes.c_int, [P, P, i32, P, P]),
         "met_decode_workspace_bytes": (ctypes.c_int, [P, i32, u32, i32, ctypes.POINTER(sz)]),
         "met_decode": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, P]),
+        "met_mdr_bob": (ctypes.c_int, [P, P, i64, i64, i32, P, P, P]),
+        "met_mdr_alice": (ctypes.c_int, [P, P, P, ctypes.c_float, i64, i64, i32, P, P]),
         "met_last_error": (ctypes.c_char_p, []),
         "met_decode_ex": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, ctypes.POINTER(met_tuning), P]),
         "met_wbp_workspace_bytes": (ctypes.c_int, [P, i32, i32, i32, ctypes.POINTER(sz)]),

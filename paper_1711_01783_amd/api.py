@@ -23,18 +23,36 @@ class Code:
         self.E = int(st.E)
         self._stats = st
 
-    @classmethod
-    def build(cls, profile, n: int, seed: int) -> "Code":
-        """From a degree profile with ``vn_types`` / ``cn_types`` rows of
-        (fraction, per-edge-type degrees)."""
+    @staticmethod
+    def _profile(profile):
         t = len(profile.vn_types[0][1])
         vfrac = (ctypes.c_double * len(profile.vn_types))(*[f for f, _ in profile.vn_types])
         vdeg = (ctypes.c_int32 * (len(profile.vn_types) * t))(*[d for _, ds in profile.vn_types for d in ds])
         cfrac = (ctypes.c_double * len(profile.cn_types))(*[f for f, _ in profile.cn_types])
         cdeg = (ctypes.c_int32 * (len(profile.cn_types) * t))(*[d for _, ds in profile.cn_types for d in ds])
-        p = met_profile(t, len(profile.vn_types), vfrac, vdeg, len(profile.cn_types), cfrac, cdeg)
+        # the arrays travel with the struct so that they outlive the call
+        return met_profile(t, len(profile.vn_types), vfrac, vdeg, len(profile.cn_types), cfrac, cdeg), \
+            (vfrac, vdeg, cfrac, cdeg)
+
+    @classmethod
+    def build(cls, profile, n: int, seed: int) -> "Code":
+        """From a degree profile with ``vn_types`` / ``cn_types`` rows of
+        (fraction, per-edge-type degrees): seeded random socket permutation."""
+        p, _keep = cls._profile(profile)
         h = ctypes.c_void_p()
         check(lib.met_code_build(ctypes.byref(p), int(n), int(seed) & (2**64 - 1), ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def build_peg(cls, profile, n: int, seed: int, depth=None) -> "Code":
+        """Progressive edge growth (met_code_build_peg); depth: search depth
+        per edge type, or None for the library's default."""
+        p, _keep = cls._profile(profile)
+        dep = None
+        if depth is not None:
+            dep = (ctypes.c_int32 * len(depth))(*[int(x) for x in depth])
+        h = ctypes.c_void_p()
+        check(lib.met_code_build_peg(ctypes.byref(p), int(n), int(seed) & (2**64 - 1), dep, ctypes.byref(h)))
         return cls(h)
 
     @classmethod
@@ -132,6 +150,37 @@ def syndrome(code: Code, bits, stream=None):
     out = torch.empty((b, code.M), dtype=torch.uint8, device=bits.device)
     check(lib.met_syndrome(code.handle, bits.data_ptr(), b, out.data_ptr(), _stream_ptr(stream)))
     return out
+
+
+def mdr_bob(y, bits, d: int = 8, stream=None):
+    """Bob's side of multidimensional reconciliation: (alpha float32 [B, N],
+    |y| float32 [B, N/d]) from his Gaussian variables y float32 [B, N] and his
+    random bits uint8 [B, N] (met_mdr_bob)."""
+    import torch
+
+    b, n = int(y.shape[0]), int(y.shape[1])
+    _require(y, torch.float32, (b, n), "y")
+    _require(bits, torch.uint8, (b, n), "bits")
+    alpha = torch.empty((b, n), dtype=torch.float32, device=y.device)
+    ynorm = torch.empty((b, max(n // d, 1)), dtype=torch.float32, device=y.device)
+    check(lib.met_mdr_bob(y.data_ptr(), bits.data_ptr(), b, n, int(d), alpha.data_ptr(), ynorm.data_ptr(),
+                          _stream_ptr(stream)))
+    return alpha, ynorm
+
+
+def mdr_alice(x, alpha, ynorm, sigma_z2: float, d: int = 8, stream=None):
+    """Alice's side: decoder LLRs float32 [B, N] from her variables x, Bob's
+    alpha and |y|, and the noise variance of y - x (met_mdr_alice)."""
+    import torch
+
+    b, n = int(x.shape[0]), int(x.shape[1])
+    _require(x, torch.float32, (b, n), "x")
+    _require(alpha, torch.float32, (b, n), "alpha")
+    _require(ynorm, torch.float32, (b, max(n // d, 1)), "ynorm")
+    llr = torch.empty((b, n), dtype=torch.float32, device=x.device)
+    check(lib.met_mdr_alice(x.data_ptr(), alpha.data_ptr(), ynorm.data_ptr(), float(sigma_z2), b, n, int(d),
+                            llr.data_ptr(), _stream_ptr(stream)))
+    return llr
 
 
 def workspace_bytes(code: Code, frames: int, fixed_iters: bool = False, posterior: bool = False,

@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmetbp.so")
-SOURCES = ["met_code.cpp", "met_decode.hip", "met_wbp.hip", "met_batched.hip"]
+SOURCES = ["met_code.cpp", "met_decode.hip", "met_wbp.hip", "met_batched.hip", "met_mdr.hip"]
 ARCH = os.environ.get("MET_OFFLOAD_ARCH", "gfx950")
 
 

@@ -29,6 +29,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <numeric>
+#include <set>
 #include <unordered_map>
 
 #include "met_internal.h"
@@ -293,10 +295,17 @@ static int sort_and_finalize(met_code *c, std::vector<int32_t> &v, std::vector<i
   return met::finalize_code(c);
 }
 
-extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out) { return met::guarded("met_code_build", [&]() -> int {
-  met::clear_error();
-  if (!p || !out) return fail(MET_EINVAL, "met_code_build: NULL argument");
-  *out = nullptr;
+// Steps 1-4, shared by both constructions: validated profile -> node counts,
+// node type of every VN, check count and the balanced per-check socket
+// counts cdeg[j * T + t].
+struct Sockets {
+  int T = 0, VT = 0;
+  int64_t M = 0;
+  std::vector<int64_t> vcount, S;
+  std::vector<int32_t> cdeg, vtype;
+};
+
+static int prepare_sockets(const met_profile *p, int64_t N, Sockets &sk) {
   const int T = p->n_edge_types;
   if (T < 1 || T > MET_MAX_EDGE_TYPES) return fail(MET_EINVAL, "n_edge_types %d outside 1..%d", T, MET_MAX_EDGE_TYPES);
   if (p->n_vn_types < 1 || p->n_cn_types < 1 || !p->vn_frac || !p->vn_deg || !p->cn_frac || !p->cn_deg)
@@ -387,13 +396,34 @@ extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, me
       return fail(MET_EINVAL, "check %lld would have degree %d (allowed 2..%d)", (long long)j, dsum,
                   MET_MAX_CHECK_DEGREE);
   }
-  // 5-6. sockets and shuffles
   std::vector<int32_t> vtype(N);
   {
     int64_t v = 0;
     for (int k = 0; k < VT; ++k)
       for (int64_t i = 0; i < vcount[k]; ++i) vtype[v++] = k;
   }
+  sk.T = T;
+  sk.VT = VT;
+  sk.M = M;
+  sk.vcount = std::move(vcount);
+  sk.S = std::move(S);
+  sk.cdeg = std::move(cdeg);
+  sk.vtype = std::move(vtype);
+  return MET_OK;
+}
+
+extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, met_code **out) { return met::guarded("met_code_build", [&]() -> int {
+  met::clear_error();
+  if (!p || !out) return fail(MET_EINVAL, "met_code_build: NULL argument");
+  *out = nullptr;
+  Sockets sk;
+  int rc0 = prepare_sockets(p, N, sk);
+  if (rc0) return rc0;
+  const int T = sk.T;
+  const int64_t M = sk.M;
+  const std::vector<int64_t> &S = sk.S;
+  const std::vector<int32_t> &cdeg = sk.cdeg, &vtype = sk.vtype;
+  // 5-6. sockets and shuffles
   std::vector<std::vector<int32_t>> vs(T), cs(T);
   std::vector<met::SplitMix64> rng;
   for (int t = 0; t < T; ++t) {
@@ -471,6 +501,256 @@ extern "C" int met_code_build(const met_profile *p, int64_t N, uint64_t seed, me
     t.insert(t.end(), vs[tt].size(), (int8_t)tt);
   }
   int rc = sort_and_finalize(code, v, ch, t);
+  if (rc != MET_OK) {
+    delete code;
+    return rc;
+  }
+  *out = code;
+  return MET_OK;
+  });
+}
+
+// Progressive edge growth (Methods, first paragraph: the paper builds its
+// matrices this way).  Edges are placed one at a time, node by node (v =
+// 0..N-1) and within a node edge type by edge type; each goes to a check as
+// far from its node as the type-t graph built so far allows:
+//   * a breadth-first search from v over the type-t edges placed so far gives
+//     check layers C_1 (v's type-t checks), C_2, ..., at most depth[t] of them,
+//     stopping at the first empty layer;
+//   * candidates are the checks with a free type-t socket that are not yet
+//     neighbours of v; for k = (number of layers) down to 1 the candidates
+//     outside C_1..C_k are taken, and the first k that leaves any decides;
+//   * among them the ones with the fewest type-t edges form the tie set, and
+//     the edge goes to its r-th check in check order, r = uniform(size) from
+//     the SplitMix64 stream numbered T (after the T streams of the random
+//     construction), one draw per edge.
+// An edge to a check of layer C_k would close a cycle of length 2k, so the
+// rule keeps cycles of length <= 2 depth[t] out of the type-t graph wherever
+// free sockets allow.  Default depths: with d_v, d_c the largest type-t
+// degrees, layer k of a full graph holds about (d_v - 1) g^(k-1) checks,
+// g = (d_v - 1)(d_c - 1); the depth is 1 if g = 0 (edges of degree-1 nodes
+// close no cycle), else the largest K <= 16 with (d_v - 1) g^(K-1) <= 1024.
+//
+// Tie sets are found with one Fenwick tree per (edge type, fill level) over
+// the checks owning that type (counts, rank and select in O(log M)); the few
+// checks a search excludes are skipped by rank.
+namespace met {
+namespace {
+
+constexpr int kPegMaxDepth = 16;
+
+int peg_default_depth(const met_profile *p, int t) {
+  const int T = p->n_edge_types;
+  int64_t dv = 0, dc = 0;
+  for (int k = 0; k < p->n_vn_types; ++k) dv = std::max<int64_t>(dv, p->vn_deg[k * T + t]);
+  for (int k = 0; k < p->n_cn_types; ++k) dc = std::max<int64_t>(dc, p->cn_deg[k * T + t]);
+  const int64_t g = std::max<int64_t>(dv - 1, 0) * std::max<int64_t>(dc - 1, 0);
+  if (g == 0) return 1;
+  int K = 1;
+  int64_t layer = (dv - 1) * g;  // size of layer K + 1
+  while (K < kPegMaxDepth && layer <= 1024) {
+    ++K;
+    layer *= g;
+  }
+  return K;
+}
+
+// Membership counts over positions 0..n-1.
+struct Fenwick {
+  std::vector<int32_t> a;
+  int32_t total = 0;
+  explicit Fenwick(int64_t n = 0) : a(n + 1, 0) {}
+  void add(int64_t i, int32_t d) {
+    total += d;
+    for (++i; i < (int64_t)a.size(); i += i & -i) a[i] += d;
+  }
+  int32_t prefix(int64_t i) const {  // members at positions < i
+    int32_t s = 0;
+    for (; i > 0; i -= i & -i) s += a[i];
+    return s;
+  }
+  int64_t select(int32_t k) const {  // position of the k-th member (0-based)
+    int64_t pos = 0;
+    int64_t step = 1;
+    while (step * 2 < (int64_t)a.size()) step *= 2;
+    for (; step > 0; step /= 2)
+      if (pos + step < (int64_t)a.size() && a[pos + step] <= k) {
+        pos += step;
+        k -= a[pos];
+      }
+    return pos;  // 0-based position
+  }
+};
+
+}  // namespace
+}  // namespace met
+
+extern "C" int met_code_build_peg(const met_profile *p, int64_t N, uint64_t seed, const int32_t *depth,
+                                  met_code **out) { return met::guarded("met_code_build_peg", [&]() -> int {
+  met::clear_error();
+  if (!p || !out) return fail(MET_EINVAL, "met_code_build_peg: NULL argument");
+  *out = nullptr;
+  Sockets sk;
+  int rc0 = prepare_sockets(p, N, sk);
+  if (rc0) return rc0;
+  const int T = sk.T;
+  const int64_t M = sk.M;
+  const std::vector<int32_t> &cdeg = sk.cdeg, &vtype = sk.vtype;
+  std::vector<int> K(T);
+  for (int t = 0; t < T; ++t) {
+    K[t] = depth ? depth[t] : met::peg_default_depth(p, t);
+    if (K[t] < 1 || K[t] > met::kPegMaxDepth)
+      return fail(MET_EINVAL, "depth[%d] = %d outside 1..%d", t, K[t], met::kPegMaxDepth);
+  }
+  met::SplitMix64 rng(met::mix64(seed ^ met::mix64((uint64_t)T + 1)));
+  // checks owning each type: one contiguous run (checks are numbered type by
+  // type and every edge type belongs to one check type)
+  std::vector<int64_t> own0(T, 0), own_n(T, 0);
+  for (int t = 0; t < T; ++t) {
+    int64_t lo = -1, hi = -1;
+    for (int64_t j = 0; j < M; ++j)
+      if (cdeg[j * T + t] > 0) {
+        if (lo < 0) lo = j;
+        if (hi >= 0 && hi != j - 1) return fail(MET_EINVAL, "checks of edge type %d are not contiguous", t);
+        hi = j;
+      }
+    own0[t] = lo < 0 ? 0 : lo;
+    own_n[t] = lo < 0 ? 0 : hi - lo + 1;
+  }
+  // type-t adjacency as it grows: flat lists with known capacities
+  std::vector<std::vector<int64_t>> vptr(T), cptr(T);
+  std::vector<std::vector<int32_t>> vlist(T), clist(T), vfill(T), cfill(T);
+  std::vector<int> max_cdeg(T, 0);
+  for (int t = 0; t < T; ++t) {
+    vptr[t].assign(N + 1, 0);
+    cptr[t].assign(M + 1, 0);
+    for (int64_t v = 0; v < N; ++v) vptr[t][v + 1] = vptr[t][v] + p->vn_deg[vtype[v] * T + t];
+    for (int64_t j = 0; j < M; ++j) {
+      cptr[t][j + 1] = cptr[t][j] + cdeg[j * T + t];
+      max_cdeg[t] = std::max(max_cdeg[t], cdeg[j * T + t]);
+    }
+    vlist[t].assign(vptr[t][N], 0);
+    clist[t].assign(cptr[t][M], 0);
+    vfill[t].assign(N, 0);
+    cfill[t].assign(M, 0);
+  }
+  // free checks of each type by fill level (positions within the owner run)
+  std::vector<std::vector<met::Fenwick>> level(T);
+  for (int t = 0; t < T; ++t) {
+    level[t].assign(max_cdeg[t], met::Fenwick(own_n[t]));
+    for (int64_t i = 0; i < own_n[t]; ++i) level[t][0].add(i, 1);
+  }
+  // stamps: search marks per edge, neighbour marks per node
+  std::vector<int64_t> cstamp(M, -1), vstamp(N, -1), nstamp(M, -1);
+  std::vector<int32_t> clayer(M, 0), frontier, nodes, next, visited, skip;
+  std::vector<int32_t> ev, ec;
+  std::vector<int8_t> et;
+  const int64_t E_total = std::accumulate(sk.S.begin(), sk.S.end(), (int64_t)0);
+  ev.reserve(E_total);
+  ec.reserve(E_total);
+  et.reserve(E_total);
+  int64_t stamp = 0;
+  for (int64_t v = 0; v < N; ++v) {
+    for (int t = 0; t < T; ++t) {
+      const int dv = p->vn_deg[vtype[v] * T + t];
+      for (int r = 0; r < dv; ++r, ++stamp) {
+        // neighbours of v (every type): never a candidate
+        visited.clear();
+        for (int tt = 0; tt < T; ++tt)
+          for (int64_t i = vptr[tt][v]; i < vptr[tt][v] + vfill[tt][v]; ++i) {
+            nstamp[vlist[tt][i]] = stamp;
+            visited.push_back(vlist[tt][i]);
+          }
+        // layers of the search over type-t edges
+        frontier.clear();
+        for (int64_t i = vptr[t][v]; i < vptr[t][v] + vfill[t][v]; ++i) {
+          const int32_t c = vlist[t][i];
+          if (cstamp[c] != stamp) {
+            cstamp[c] = stamp;
+            clayer[c] = 1;
+            frontier.push_back(c);
+            visited.push_back(c);
+          }
+        }
+        vstamp[v] = stamp;
+        int layers = 1;
+        while (layers < K[t]) {
+          nodes.clear();
+          for (int32_t c : frontier)
+            for (int64_t i = cptr[t][c]; i < cptr[t][c] + cfill[t][c]; ++i) {
+              const int32_t u = clist[t][i];
+              if (vstamp[u] != stamp) {
+                vstamp[u] = stamp;
+                nodes.push_back(u);
+              }
+            }
+          next.clear();
+          for (int32_t u : nodes)
+            for (int64_t i = vptr[t][u]; i < vptr[t][u] + vfill[t][u]; ++i) {
+              const int32_t c = vlist[t][i];
+              if (cstamp[c] != stamp) {
+                cstamp[c] = stamp;
+                clayer[c] = layers + 1;
+                next.push_back(c);
+                visited.push_back(c);
+              }
+            }
+          if (next.empty()) break;
+          ++layers;
+          frontier.swap(next);
+        }
+        // the deepest level that leaves a candidate decides; the least filled
+        // candidates form the tie set, in check order
+        int32_t chosen = -1;
+        for (int k = layers; k >= 1 && chosen < 0; --k) {
+          for (int f = 0; f < max_cdeg[t] && chosen < 0; ++f) {
+            const met::Fenwick &fw = level[t][f];
+            if (fw.total == 0) continue;
+            // excluded members of this level, in check order (no repeats)
+            skip.clear();
+            for (int32_t c : visited) {
+              const bool excl = nstamp[c] == stamp || (cstamp[c] == stamp && clayer[c] <= k);
+              if (!excl || c < own0[t] || c >= own0[t] + own_n[t]) continue;
+              if (cfill[t][c] != f || cfill[t][c] >= cdeg[(int64_t)c * T + t]) continue;
+              skip.push_back(c);
+            }
+            std::sort(skip.begin(), skip.end());
+            skip.erase(std::unique(skip.begin(), skip.end()), skip.end());
+            const int32_t count = fw.total - (int32_t)skip.size();
+            if (count <= 0) continue;
+            int32_t want = (int32_t)rng.uniform((uint64_t)count);
+            for (int32_t c : skip) {  // rank among the level's members, skipping excluded ones
+              if (fw.prefix(c - own0[t]) <= want)
+                ++want;
+              else
+                break;
+            }
+            chosen = (int32_t)(own0[t] + fw.select(want));
+          }
+        }
+        if (chosen < 0)
+          return fail(MET_EINVAL, "no check left for an edge of type %d of node %lld", t, (long long)v);
+        const int f = cfill[t][chosen];
+        level[t][f].add(chosen - own0[t], -1);
+        if (f + 1 < cdeg[(int64_t)chosen * T + t]) level[t][f + 1].add(chosen - own0[t], 1);
+        vlist[t][vptr[t][v] + vfill[t][v]++] = chosen;
+        clist[t][cptr[t][chosen] + cfill[t][chosen]++] = (int32_t)v;
+        ev.push_back((int32_t)v);
+        ec.push_back(chosen);
+        et.push_back((int8_t)t);
+      }
+    }
+  }
+  for (int t = 0; t < T; ++t)
+    for (int64_t j = 0; j < M; ++j)
+      if (cfill[t][j] != cdeg[j * T + t]) return fail(MET_EINVAL, "sockets of edge type %d left unfilled", t);
+  met_code *code = new (std::nothrow) met_code();
+  if (!code) return fail(MET_ENOMEM, "out of host memory");
+  code->uid = g_next_uid.fetch_add(1) + 1;
+  code->N = N;
+  code->M = M;
+  code->ntypes = T;
+  int rc = sort_and_finalize(code, ev, ec, et);
   if (rc != MET_OK) {
     delete code;
     return rc;

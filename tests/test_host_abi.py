@@ -248,3 +248,44 @@ def test_batched_autotune_validation_without_gpu():
     assert L.met_batched_autotune(jobs, 1, P(264), n.value, 0, ctypes.byref(best), None, None) == -1
     assert L.met_batched_autotune(jobs, 1, P(256), n.value - 1, 0, ctypes.byref(best), None, None) == -1
     assert L.met_batched_autotune(jobs, 0, P(256), n.value, 0, ctypes.byref(best), None, None) == -1
+
+
+def test_mdr_argument_validation_without_gpu():
+    """Front-end entry points validate before any HIP call."""
+    L = _lib.lib
+    P = ctypes.c_void_p
+    d16, d8 = P(4096), P(4096 + 8)
+    assert L.met_mdr_bob(d16, d16, 2, 64, 3, d16, d16, None) == -1        # dimension
+    assert "dimension" in L.met_last_error().decode()
+    assert L.met_mdr_bob(d16, d16, 2, 60, 8, d16, d16, None) == -1        # N not a multiple of d
+    assert L.met_mdr_bob(d16, d16, 0, 64, 8, d16, d16, None) == -1        # B
+    assert L.met_mdr_bob(None, d16, 2, 64, 8, d16, d16, None) == -1       # NULL
+    assert L.met_mdr_bob(d8, d16, 2, 64, 8, d16, d16, None) == -1         # y not 16-byte aligned
+    assert L.met_mdr_bob(d16, P(4097), 2, 64, 8, d16, d16, None) == -1    # bits not 8-byte aligned
+    assert L.met_mdr_bob(d16, d16, 1 << 20, 1 << 20, 8, d16, d16, None) == -1  # B N above 2^36
+    assert L.met_mdr_alice(d16, d16, d16, 0.0, 2, 64, 8, d16, None) == -1     # sigma^2 <= 0
+    assert L.met_mdr_alice(d16, d16, d16, float("nan"), 2, 64, 8, d16, None) == -1
+    assert L.met_mdr_alice(d16, d8, d16, 1.0, 2, 64, 8, d16, None) == -1      # alpha misaligned
+    assert L.met_mdr_alice(d16, d16, d16, 1.0, 2, 64, 5, d16, None) == -1     # dimension
+
+
+@pytest.mark.parametrize("name,n,seed,depth", [("r0.1", 4096, 1, None), ("r0.05", 4096, 2, None),
+                                               ("r0.02", 4096, 3, None), ("r0.1", 8192, 4, [4, 1, 1]),
+                                               ("r0.02", 8192, 5, [2, 2, 1])])
+def test_cpp_peg_matches_oracle(name, n, seed, depth):
+    """The C++ progressive-edge-growth builder equals oracle/peg.py bit for bit."""
+    from oracle import peg
+
+    cg = met.Code.build_peg(PROFILES[name], n, seed, depth)
+    vn, cn, et = cg.export()
+    co = peg.build(PROFILES[name], n, seed, depth)
+    np.testing.assert_array_equal(vn, co.v)
+    np.testing.assert_array_equal(cn, co.c)
+    np.testing.assert_array_equal(et, co.t)
+
+
+def test_peg_validation():
+    with pytest.raises(met.MetError, match="depth"):
+        met.Code.build_peg(PROFILES["r0.1"], 4096, 1, [0, 1, 1])
+    with pytest.raises(met.MetError, match="depth"):
+        met.Code.build_peg(PROFILES["r0.1"], 4096, 1, [17, 1, 1])
