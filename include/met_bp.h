@@ -250,6 +250,30 @@ int met_decode(const met_code *c, const float *llr, const uint8_t *syn, int32_t 
                uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
                void *workspace, size_t ws_bytes, void *stream);
 
+/* met_decode for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * same decoder, arguments and results as met_decode without the workspace
+ * arguments: the workspace is a fixed array of MET_NOALLOC_SCRATCH_BYTES bytes
+ * inside the library, one per device, held from the library's first use of a
+ * device until the process ends.  No call allocates, frees or uploads:
+ *   - the code's adjacency must already be on the current device (an earlier
+ *     met_decode or met_syndrome on that device uploads it); else MET_ESTATE;
+ *   - decodes whose workspace (met_decode_workspace_bytes) exceeds the array
+ *     fail with MET_EINVAL (without posteriors the array holds, at the three
+ *     profiles' sizes, N = 65536 with up to 192 frames, N = 2^18 with 32,
+ *     N = 10^6 with 4);
+ *   - MET_NO_DEG1_SKIP (which builds a second layout) is MET_EINVAL;
+ *   - per-launch timing must be off (it creates events); else MET_ESTATE.
+ * Every call on a device shares that device's array and leaves its contents
+ * behind (every decode initialises what it reads): calls that overlap in time
+ * on one device, on any streams, race and give wrong results; order them on
+ * one stream or synchronise in between.  Errors: MET_EINVAL, MET_ESTATE,
+ * MET_EHIP. */
+#define MET_NOALLOC_SCRATCH_BYTES (256u << 20)
+int met_decode_noalloc(const met_code *c, const float *llr, const uint8_t *syn, int32_t B, int32_t max_iter,
+                       uint32_t flags, uint8_t *bits, int32_t *iters, uint8_t *converged, float *posterior,
+                       void *stream);
+
 /* Measurement support (not part of decoding).  While enabled, every kernel
  * launched by met_decode in this process is bracketed by two HIP events
  * recorded on the caller's stream, the stream the kernel runs on.

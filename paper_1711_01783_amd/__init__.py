@@ -17,7 +17,7 @@ from ._lib import (
     lib,
     library_path,
 )
-from .api import (BatchedDecoder, Code, DecodeOutput, Job, batched_workspace_bytes, decode, decode_batched, mdr_alice, mdr_bob,
+from .api import (BatchedDecoder, Code, DecodeOutput, Job, batched_workspace_bytes, decode, decode_batched, decode_noalloc, mdr_alice, mdr_bob,
                   syndrome,
                   timing_collect, timing_enable, workspace_bytes)
 
@@ -28,6 +28,7 @@ __all__ = [
     "Job",
     "batched_workspace_bytes",
     "decode_batched",
+    "decode_noalloc",
     "mdr_alice",
     "mdr_bob",
     "MET_EARLY_EXIT",

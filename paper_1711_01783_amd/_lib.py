@@ -18,6 +18,7 @@ MET_NO_COMPACT = 2
 MET_NO_DEG1_SKIP = 4
 MET_C2V_FP16 = 8
 MET_MAX_EDGE_TYPES = 8
+MET_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 _ERRNAMES = {MET_EINVAL: "MET_EINVAL", MET_ENOMEM: "MET_ENOMEM", MET_EHIP: "MET_EHIP", MET_ESTATE: "MET_ESTATE"}
 
@@ -105,6 +106,7 @@ def _load():
         "met_decode": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, P]),
         "met_mdr_bob": (ctypes.c_int, [P, P, i64, i64, i32, P, P, P]),
         "met_mdr_alice": (ctypes.c_int, [P, P, P, ctypes.c_float, i64, i64, i32, P, P]),
+        "met_decode_noalloc": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P]),
         "met_last_error": (ctypes.c_char_p, []),
         "met_decode_ex": (ctypes.c_int, [P, P, P, i32, i32, u32, P, P, P, P, P, sz, ctypes.POINTER(met_tuning), P]),
         "met_wbp_workspace_bytes": (ctypes.c_int, [P, i32, i32, i32, ctypes.POINTER(sz)]),

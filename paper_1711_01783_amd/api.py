@@ -243,6 +243,32 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
     return DecodeOutput(bits, iters, conv, post)
 
 
+def decode_noalloc(code: Code, llr, syn, max_iter: int, bits, iterations, converged, posterior=None,
+                   fixed_iters: bool = False, stream=None) -> None:
+    """met_decode_noalloc: decode into caller-provided outputs (bits uint8
+    [B, N], iterations int32 [B], converged uint8 [B], posterior float32 [B, N]
+    or None) with the library's fixed device workspace; nothing is allocated
+    here or in the library.  The code must already be on the device (any
+    decode or syndrome call there uploads it)."""
+    import torch
+
+    b = int(llr.shape[0])
+    _require(llr, torch.float32, (b, code.N), "llr")
+    _require(syn, torch.uint8, (b, code.M), "syn")
+    _require(bits, torch.uint8, (b, code.N), "bits")
+    _require(iterations, torch.int32, (b,), "iterations")
+    _require(converged, torch.uint8, (b,), "converged")
+    if posterior is not None:
+        _require(posterior, torch.float32, (b, code.N), "posterior")
+    check(
+        lib.met_decode_noalloc(
+            code.handle, llr.data_ptr(), syn.data_ptr(), b, int(max_iter), MET_FIXED_ITERS if fixed_iters else 0,
+            bits.data_ptr(), iterations.data_ptr(), converged.data_ptr(),
+            None if posterior is None else posterior.data_ptr(), _stream_ptr(stream),
+        )
+    )
+
+
 @dataclass
 class Job:
     """One decode job of a batched call: a code, its frames and a budget."""

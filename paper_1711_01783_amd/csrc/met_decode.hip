@@ -580,6 +580,69 @@ extern "C" int met_decode(const met_code *c, const float *llr, const uint8_t *sy
   });
 }
 
+// ---- Decoding without allocation ------------------------------------------
+// The workspace of met_decode_noalloc lives in a fixed device array of this
+// translation unit.  Host code never uses the array's name as an address (on
+// the host it is only a stand-in): the device address is looked up once per
+// device with hipGetSymbolAddress and kept.
+namespace {
+constexpr size_t kScratchBytes = (size_t)MET_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[met::kMaxDevices] = {};
+
+int scratch_address(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= met::kMaxDevices) return fail(MET_EINVAL, "device %d beyond %d", dev, met::kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(MET_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    if (!ptr || ((uintptr_t)ptr & 255)) return fail(MET_EHIP, "scratch array at %p is not 256-byte aligned", ptr);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MET_OK;
+}
+}  // namespace
+
+extern "C" int met_decode_noalloc(const met_code *c, const float *llr, const uint8_t *syn, int32_t B,
+                                  int32_t max_iter, uint32_t flags, uint8_t *bits, int32_t *iters,
+                                  uint8_t *converged, float *posterior, void *stream) { return met::guarded("met_decode_noalloc", [&]() -> int {
+  met::clear_error();
+  int rc = validate_decode(c, B, flags);
+  if (rc) return rc;
+  if (flags & MET_NO_DEG1_SKIP)
+    return fail(MET_EINVAL, "MET_NO_DEG1_SKIP builds a second layout of the code (allocates): not here");
+  const met::Plan pl = met::make_plan(c, B, posterior != nullptr, false, met::choose_interleave(B), c2v_bytes(flags));
+  if (pl.total > kScratchBytes)
+    return fail(MET_EINVAL, "decode needs %zu bytes of workspace, the fixed scratch array holds %zu", pl.total,
+                kScratchBytes);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= met::kMaxDevices) return fail(MET_EINVAL, "device %d beyond %d", dev, met::kMaxDevices);
+  {
+    // the adjacency must already be on this device: uploading it allocates
+    std::lock_guard<std::mutex> lock(const_cast<met_code *>(c)->mu);
+    if (!c->dev[dev].ready)
+      return fail(MET_ESTATE, "the code's adjacency is not on device %d yet (a met_decode or met_syndrome call "
+                  "on that device uploads it)", dev);
+  }
+  {
+    std::lock_guard<std::mutex> lock(met::g_timing.mu);
+    if (met::g_timing.on) return fail(MET_ESTATE, "per-launch timing is on (it creates HIP events)");
+  }
+  void *ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc) return rc;
+  return met_decode_ex(c, llr, syn, B, max_iter, flags, bits, iters, converged, posterior, ws, kScratchBytes,
+                       nullptr, stream);
+  });
+}
+
 extern "C" int met_timing_enable(int32_t on) { return met::guarded("met_timing_enable", [&]() -> int {
   met::clear_error();
   std::lock_guard<std::mutex> lock(met::g_timing.mu);

@@ -269,6 +269,22 @@ def test_mdr_argument_validation_without_gpu():
     assert L.met_mdr_alice(d16, d16, d16, 1.0, 2, 64, 5, d16, None) == -1     # dimension
 
 
+def test_noalloc_validation_without_gpu():
+    """The allocation-free decode refuses what it cannot do before any HIP call."""
+    c = met.Code.build(PROFILES["r0.1"], 4096, 1)
+    L = _lib.lib
+    dummy = ctypes.c_void_p(256)
+    assert L.met_decode_noalloc(None, dummy, dummy, 4, 10, 0, dummy, dummy, dummy, None, None) == -1
+    assert L.met_decode_noalloc(c.handle, dummy, dummy, 0, 10, 0, dummy, dummy, dummy, None, None) == -1
+    assert L.met_decode_noalloc(c.handle, dummy, dummy, 4, 10, 4, dummy, dummy, dummy, None, None) == -1
+    assert "MET_NO_DEG1_SKIP" in L.met_last_error().decode()
+    n = ctypes.c_size_t()
+    assert L.met_decode_workspace_bytes(c.handle, 60000, 0, 0, ctypes.byref(n)) == 0
+    assert n.value > _lib.MET_NOALLOC_SCRATCH_BYTES
+    assert L.met_decode_noalloc(c.handle, dummy, dummy, 60000, 10, 0, dummy, dummy, dummy, None, None) == -1
+    assert "scratch" in L.met_last_error().decode()
+
+
 @pytest.mark.parametrize("name,n,seed,depth", [("r0.1", 4096, 1, None), ("r0.05", 4096, 2, None),
                                                ("r0.02", 4096, 3, None), ("r0.1", 8192, 4, [4, 1, 1]),
                                                ("r0.02", 8192, 5, [2, 2, 1])])
