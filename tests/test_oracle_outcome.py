@@ -53,3 +53,17 @@ def test_missed_convergence_on_a_stable_frame_is_rejected(case):
     conv[3], it[3] = 0, 40
     with pytest.raises(AssertionError, match="flag differs"):
         oo.compare(code, llr, syn, 40, bits, conv, it)
+
+
+def test_late_flag_difference_is_a_frame_error_of_one_side(case):
+    """One side converging after more than half the budget, the other not at
+    all: accepted and listed (such frames are compared through the FER)."""
+    code, llr, syn, r = case
+    ref = oo.oracle_outcomes(code, llr, syn, 40)
+    ref["converged"] = ref["converged"].copy()
+    ref["iterations"] = ref["iterations"].copy()
+    ref["converged"][4], ref["iterations"][4] = 0, 40   # as if the oracle had not converged
+    it = r.iterations.copy()
+    it[4] = 31                                          # and the decoder only late
+    acc, rep = oo.compare(code, llr, syn, 40, r.bits, r.converged, it, ref=ref)
+    assert acc == [4] and "late convergence" in rep[0]
