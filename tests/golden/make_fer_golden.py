@@ -1,13 +1,15 @@
 """Writes the oracle's per-frame outcomes used by the GPU FER-parity test.
 
-    python tests/golden/make_fer_golden.py [--frames 1024] [--workers 8]
+    python tests/golden/make_fer_golden.py [--frames 1024] [--workers 8] [--construction peg]
 
 Calls only the FP64 oracle (`oracle/`) and the seeded input module
-(`met_inputs`).  For each rate: the code built by `oracle.code.build` from the
-profile with CODE_SEED, N = 65536, frames FRAME_SEED + f at the waterfall SNR,
-decoded in early-exit mode with the rate's iteration budget.  Stored per frame:
-converged flag, iterations, frame error (decoded bits != sent bits) and the
-SHA-1 of the decoded bits.
+(`met_inputs`).  For each rate: the code built from the profile with CODE_SEED
+at N = 65536 by `oracle.code.build` (the seeded random construction; files
+fer_<rate>_N65536.json) or by `oracle.peg.build` at its default depths
+(progressive edge growth; files fer_peg_<rate>_N65536.json), frames
+FRAME_SEED + f at the waterfall SNR, decoded in early-exit mode with the
+rate's iteration budget.  Stored per frame: converged flag, iterations, frame
+error (decoded bits != sent bits) and the SHA-1 of the decoded bits.
 """
 import argparse
 import hashlib
@@ -22,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from met_inputs import ITER_BUDGET, PROFILES, WATERFALL_SNR, make_frames  # noqa: E402
-from oracle import bp, code as oc  # noqa: E402
+from oracle import bp, code as oc, peg  # noqa: E402
 
 N = 65536
 CODE_SEED = 31
@@ -54,14 +56,20 @@ def main():
     ap.add_argument("--frames", type=int, default=1024)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--rates", default="r0.1,r0.05,r0.02")
+    ap.add_argument("--construction", choices=("random", "peg"), default="random")
     args = ap.parse_args()
     for prof in args.rates.split(","):
-        _CODE[prof] = oc.build(PROFILES[prof], N, CODE_SEED)
+        if args.construction == "peg":
+            _CODE[prof] = peg.build(PROFILES[prof], N, CODE_SEED)
+        else:
+            _CODE[prof] = oc.build(PROFILES[prof], N, CODE_SEED)
         jobs = [(prof, f0, min(CHUNK, args.frames - f0)) for f0 in range(0, args.frames, CHUNK)]
         with mp.get_context("fork").Pool(args.workers) as pool:
             frames = [x for part in pool.map(_work, jobs) for x in part]
         rec = {
             "source": "oracle/bp.py early-exit decode; tests/golden/make_fer_golden.py",
+            "construction": args.construction,
+            "peg_depth": peg.default_depths(PROFILES[prof]) if args.construction == "peg" else None,
             "profile": prof,
             "N": N,
             "code_seed": CODE_SEED,
@@ -70,7 +78,8 @@ def main():
             "max_iter": ITER_BUDGET[prof],
             "frames": frames,
         }
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fer_%s_N%d.json" % (prof, N))
+        stem = "fer_peg_%s_N%d.json" if args.construction == "peg" else "fer_%s_N%d.json"
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), stem % (prof, N))
         with open(path, "w") as f:
             json.dump(rec, f, separators=(",", ":"))
         fer = sum(x["frame_error"] for x in frames) / len(frames)
