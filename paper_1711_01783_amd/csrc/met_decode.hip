@@ -54,6 +54,14 @@ constexpr int kCompactEvery = 4;    // iterations between compaction points
 constexpr int kCompactMinLeft = 4;  // no compaction this close to the budget
 constexpr int kMaxGroups = 1024;    // 65535 frames in groups of 64
 
+// flag = 1 if any frame of any group still runs (one block).
+__global__ __launch_bounds__(kBlock) void k_any_active(const uint64_t *active, int G, uint32_t *flag) {
+  uint64_t any = 0;
+  for (int g = threadIdx.x; g < G; g += kBlock) any |= active[g];
+  const int r = __syncthreads_or(any != 0ull);
+  if (threadIdx.x == 0) *flag = (uint32_t)r;
+}
+
 struct CompactView {
   int32_t *n_dest, *dest, *src;  // header, receiving groups, [n_dest][64] source slots
 };
@@ -315,6 +323,20 @@ struct Decoder {
     fp.slot_frame = slot_frame;
     fp.G = G;
     const int base_flags = (post ? F_POST : 0) | (weights ? F_WEIGHTED : 0);
+    // Early stop of the launch sequence: in early-exit mode the host reads
+    // whether any frame still runs after iterations 4, 8, 16, ... (a stream
+    // synchronisation each, so a doubling schedule); once none does, the
+    // remaining iterations would launch kernels with nothing to do, and the
+    // final test and outputs follow at once.  Not while the stream is being
+    // captured into a graph (no synchronisation is possible there).
+    bool can_stop = early;
+    if (can_stop) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      HIP_TRY(hipStreamIsCapturing(st, &cs));
+      can_stop = cs == hipStreamCaptureStatusNone;
+    }
+    int next_check = 4;
+    uint32_t *flag = at<uint32_t>(pl.off_flag);
 
     for (int it = 1; it <= max_iter; ++it) {
       cp.it = it;
@@ -368,6 +390,14 @@ struct Decoder {
         move(Lphi, c->EL);
         move_bits(synw, c->M);
         move_bits(B1 + (size_t)(it & 1) * leaf_words, c->EL);
+      }
+      if (can_stop && it == next_check && it < max_iter) {
+        next_check *= 2;
+        hipLaunchKernelGGL(k_any_active, dim3(1), dim3(kBlock), 0, st, active, G, flag);
+        uint32_t any = 1;
+        HIP_TRY(hipMemcpyAsync(&any, flag, sizeof any, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (!any) break;  // every frame has stopped
       }
     }
     TestParams tp{};

@@ -812,7 +812,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Plan {
   int W = 64, G = 1;
   size_t off_c2v = 0, off_P = 0, off_L2 = 0, off_Lphi = 0, off_Lraw = 0, off_P1 = 0, off_synw = 0, off_B1 = 0,
-         off_unsat = 0, off_active = 0, off_slot = 0, off_ctab = 0, total = 0;
+         off_unsat = 0, off_active = 0, off_slot = 0, off_ctab = 0, off_flag = 0, total = 0;
   bool lraw = false, p1 = false;
 };
 
@@ -856,6 +856,7 @@ Plan make_plan(const met_code *c, int B, bool post, bool weighted, int W, size_t
   pl.off_active = take((size_t)pl.G * sizeof(uint64_t));
   pl.off_slot = take(GW * sizeof(int32_t));
   pl.off_ctab = take(compact_table_bytes(pl.G));
+  pl.off_flag = take(sizeof(uint32_t));
   pl.total = o;
   return pl;
 }

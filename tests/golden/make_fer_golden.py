@@ -51,18 +51,41 @@ def _work(args):
     return out
 
 
+def code_sha1(code) -> str:
+    """SHA-1 of the edge list (variable, check, type as int64, in the code's
+    (check, type, variable) order): lets a test check that another builder made
+    exactly this graph."""
+    h = hashlib.sha1()
+    for a in (code.v, code.c, code.t):
+        h.update(np.ascontiguousarray(a, dtype=np.int64).tobytes())
+    return h.hexdigest()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=1024)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--rates", default="r0.1,r0.05,r0.02")
     ap.add_argument("--construction", choices=("random", "peg"), default="random")
+    ap.add_argument("--add-code-hash", action="store_true",
+                    help="only build each code and store its edge-list SHA-1 in the existing file")
     args = ap.parse_args()
     for prof in args.rates.split(","):
         if args.construction == "peg":
             _CODE[prof] = peg.build(PROFILES[prof], N, CODE_SEED)
         else:
             _CODE[prof] = oc.build(PROFILES[prof], N, CODE_SEED)
+        stem = "fer_peg_%s_N%d.json" if args.construction == "peg" else "fer_%s_N%d.json"
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), stem % (prof, N))
+        if args.add_code_hash:
+            with open(path) as f:
+                rec = json.load(f)
+            assert rec["code_seed"] == CODE_SEED and rec["N"] == N
+            rec["code_sha1"] = code_sha1(_CODE[prof])
+            with open(path, "w") as f:
+                json.dump(rec, f, separators=(",", ":"))
+            print(prof, "code_sha1", rec["code_sha1"], "->", path, flush=True)
+            continue
         jobs = [(prof, f0, min(CHUNK, args.frames - f0)) for f0 in range(0, args.frames, CHUNK)]
         with mp.get_context("fork").Pool(args.workers) as pool:
             frames = [x for part in pool.map(_work, jobs) for x in part]
@@ -71,6 +94,7 @@ def main():
             "construction": args.construction,
             "peg_depth": peg.default_depths(PROFILES[prof]) if args.construction == "peg" else None,
             "profile": prof,
+            "code_sha1": code_sha1(_CODE[prof]),
             "N": N,
             "code_seed": CODE_SEED,
             "frame_seed": FRAME_SEED,
@@ -78,8 +102,6 @@ def main():
             "max_iter": ITER_BUDGET[prof],
             "frames": frames,
         }
-        stem = "fer_peg_%s_N%d.json" if args.construction == "peg" else "fer_%s_N%d.json"
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), stem % (prof, N))
         with open(path, "w") as f:
             json.dump(rec, f, separators=(",", ":"))
         fer = sum(x["frame_error"] for x in frames) / len(frames)
