@@ -324,6 +324,13 @@ int met_wbp_backward(const met_code *c, const float *grad_posterior, int32_t B, 
  * selects the default. */
 #define MET_BATCH_NO_STAGGER 1u /* batched: all jobs start in the same phase */
 #define MET_BATCH_NO_GRAPH 2u   /* batched: plain launches instead of a HIP graph */
+#define MET_BATCH_PHASE_LAUNCHES 4u /* batched: one launch per phase instead of
+                                   one persistent launch: every launch holds the
+                                   tiles of every job in that phase (the kernel
+                                   boundary is the barrier); captured in the
+                                   same HIP graph.  Same results.  Launches of
+                                   jobs whose frames have all stopped still run
+                                   (their tiles return at once) */
 
 typedef struct {
   int32_t check_steps_per_wave; /* 1, 2 or 4: steps of 64/W checks each wave of
@@ -384,7 +391,8 @@ int met_batched_check(const void *workspace, int32_t *barrier_expired);
 /* Autotuner of the batched launch: times candidate launch shapes (check steps
  * per wave 4/2/1 x resident blocks per compute unit 6..2 with groups of 64
  * frames, and blocks per compute unit 6/4/2 with groups of 32 and of 16, then
- * the stagger of the fastest) on the same jobs with every budget capped at probe_iters
+ * the stagger of the fastest; then one launch per phase, MET_BATCH_PHASE_LAUNCHES,
+ * for the same widths and steps, staggered or not) on the same jobs with every budget capped at probe_iters
  * iterations (0 selects 6), discards shapes whose barrier expired, and writes
  * the fastest to *best (its time per probe run to *best_ms if not NULL).
  * Synchronises `stream`; overwrites the jobs' outputs.  Results are cached per

@@ -65,6 +65,7 @@ class met_kernel_time(ctypes.Structure):
 
 MET_BATCH_NO_STAGGER = 1
 MET_BATCH_NO_GRAPH = 2
+MET_BATCH_PHASE_LAUNCHES = 4
 
 
 class met_tuning(ctypes.Structure):

@@ -1,5 +1,6 @@
 // Batched decoding: several jobs (each a code, a batch of frames and an
-// iteration budget) in one persistent launch, captured in a HIP graph.
+// iteration budget) in one HIP graph, run either as one persistent launch or
+// as one launch per phase (MET_BATCH_PHASE_LAUNCHES); the autotuner picks.
 //
 // The iterations of every job (Methods, Steps 3-5) run inside one kernel as a
 // sequence of phases separated by a grid-wide barrier.  A job's check update
@@ -15,6 +16,18 @@
 // at most 6 blocks per compute unit), which the barrier needs.  The barrier's
 // wait is bounded: if it ever expires (blocks not co-resident), an error flag is
 // set, every block returns at its next barrier, and met_batched_check reports it.
+//
+// With one launch per phase the same tile bodies run in ordinary launches, one
+// per phase with the tiles of every job in that phase; the kernel boundary is
+// the barrier and the hardware dispatcher hands out the tiles.  Where every
+// phase fills the GPU (the three codes at N = 10^6) this is the faster
+// schedule: the persistent launch pays a grid barrier and a tail per phase,
+// and its resident blocks keep one fixed order of preference in the compute
+// units' issue arbitration for the whole phase (the oldest block of a compute
+// unit completes 2.3 times the check tiles of the youngest), while short
+// ordinary blocks rotate it.  The persistent launch wins where phases are
+// short and frames converge: it stops at the first barrier after every frame
+// has stopped, while a graph of launches runs to the end.
 #include "met_gpu.h"
 
 namespace met {
@@ -333,6 +346,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
   }
 }
 
+// The same phases as separate launches (MET_BATCH_PHASE_LAUNCHES): block b
+// takes the b-th tile of the phase, the jobs' tiles one job after the other;
+// the kernel boundary replaces the grid barrier and the hardware dispatcher
+// the tile claims.  Blocks are short-lived, so the hardware's preference for
+// older waves rotates over the blocks instead of fixing the order of the
+// resident ones for a whole phase.
+template <int IPW, bool GEN, int W>
+__global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_jobs, int phase) {
+  CJob *jobs = (CJob *)table;
+  int64_t t = blockIdx.x;
+  for (int j = 0; j < n_jobs; ++j) {
+    int l = 0, kind = 0;
+    const int64_t cnt = job_tiles(jobs, j, phase, &l, &kind);
+    if (t < cnt) {
+      if (kind == 0)
+        check_tile<IPW, GEN, W>(jobs, j, l, t);
+      else
+        variable_tile<W>(jobs, j, l, t);
+      return;
+    }
+    t -= cnt;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero_floats(float *x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) x[i] = 0.0f;
 }
@@ -407,13 +444,21 @@ struct Batched {
   int n;
   char *ws;
   hipStream_t st;
-  int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1, W = 64;
+  int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1, W = 64, phases = 0;
   BatchLayout L;
   std::vector<BatchJob> table;
   std::vector<const DeviceCode *> dev;
   int n_phases = 0;
   unsigned grid = 0;
   bool gen = false;  // some class has no compiled shape
+
+  const void *phase_kernel() const {
+    if (W == 32) return gen ? (const void *)k_phase<1, true, 32> : (const void *)k_phase<1, false, 32>;
+    if (W == 16) return gen ? (const void *)k_phase<1, true, 16> : (const void *)k_phase<1, false, 16>;
+    if (gen) return (const void *)k_phase<1, true, 64>;
+    return ipw == 4 ? (const void *)k_phase<4, false, 64>
+                    : ipw == 2 ? (const void *)k_phase<2, false, 64> : (const void *)k_phase<1, false, 64>;
+  }
 
   const void *kernel() const {
     if (W == 32) return gen ? (const void *)k_persistent<1, true, 32> : (const void *)k_persistent<1, false, 32>;
@@ -571,7 +616,22 @@ struct Batched {
     char *ctl = ws + L.off_barrier;
     const BatchJob *tab = reinterpret_cast<const BatchJob *>(ws + L.off_table);
     hipLaunchKernelGGL(k_control_init, dim3(1), dim3(kBlock), 0, st, reinterpret_cast<uint32_t *>(ctl));
-    {
+    if (phases) {
+      const void *kp = phase_kernel();
+      for (int ph = 0; ph < n_phases; ++ph) {
+        int64_t tiles = 0;
+        for (int j = 0; j < n; ++j) {
+          const BatchJob &b = table[j];
+          const int s = ph - b.offset;
+          if (s >= 0 && s < 2 * b.max_iter) tiles += (int64_t)((s & 1) == 0 ? b.cn_tiles : b.vn_blocks) * b.G;
+        }
+        if (tiles == 0) continue;
+        ScopedTimer t(st, "k_phase");
+        int phv = ph;
+        void *args[] = {(void *)&tab, (void *)&n, (void *)&phv};
+        (void)hipLaunchKernel(kp, dim3((unsigned)tiles), dim3(kBlock), args, 0, st);
+      }
+    } else {
       ScopedTimer t(st, "k_persistent");
       void *args[] = {(void *)&tab, (void *)&n, (void *)&n_phases, (void *)&ctl};
       (void)hipLaunchKernel(kernel(), dim3(grid), dim3(kBlock), args, 0, st);
@@ -633,6 +693,7 @@ struct Batched {
     (void)hipGetDevice(&dev);
     append_bytes(k, dev);
     append_bytes(k, ipw);
+    append_bytes(k, phases);
     append_bytes(k, W);
     append_bytes(k, gen);
     append_bytes(k, grid);
@@ -744,9 +805,10 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
     if (s) b.ipw = s;
     if (tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > 64) return fail(MET_EINVAL, "bad blocks_per_cu");
     b.blocks_per_cu = tuning->blocks_per_cu;
-    if (tuning->batch_flags & ~3) return fail(MET_EINVAL, "unknown batch_flags");
+    if (tuning->batch_flags & ~7u) return fail(MET_EINVAL, "unknown batch_flags");
     b.stagger = !(tuning->batch_flags & MET_BATCH_NO_STAGGER);
     b.use_graph = !(tuning->batch_flags & MET_BATCH_NO_GRAPH);
+    b.phases = (tuning->batch_flags & MET_BATCH_PHASE_LAUNCHES) ? 1 : 0;
     const int w = tuning->interleave;
     if (w != 0 && w != 16 && w != 32 && w != 64) return fail(MET_EINVAL, "interleave must be 0, 16, 32 or 64");
     if (w) b.W = w;
@@ -881,6 +943,23 @@ extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *w
       cur_ms = ms;
     }
   }
+  // one launch per phase: interleave width x steps per wave x stagger
+  for (int w : met::kBatchWidths)
+    for (int ipw : {4, 2, 1})
+      for (uint32_t stag : {0u, (uint32_t)MET_BATCH_NO_STAGGER}) {
+        if (w != 64 && ipw != 1) continue;
+        met_tuning t{};
+        t.interleave = w;
+        t.check_steps_per_wave = ipw;
+        t.batch_flags = MET_BATCH_PHASE_LAUNCHES | stag;
+        float ms = 0.0f;
+        rc = met::time_shape(probe, ws, st, t, 2, &ms);
+        if (rc) return rc;
+        if (ms > 0.0f && ms < cur_ms) {
+          cur = t;
+          cur_ms = ms;
+        }
+      }
   {
     std::lock_guard<std::mutex> lock(met::g_tune_mu);
     met::g_tune.push_back({key, cur, cur_ms});

@@ -1,9 +1,10 @@
-"""Batched persistent decoding: every job's outputs equal met_decode's.
+"""Batched decoding: every job's outputs equal met_decode's.
 
 The batched launch runs the same check and variable updates as met_decode
 (Methods, Steps 3-5) for several jobs at once, interleaved phase by phase
-inside one persistent kernel.  Its results must not differ in a single bit or
-iteration count from decoding each job on its own, for any launch shape.
+inside one persistent kernel or one launch per phase.  Its results must not
+differ in a single bit or iteration count from decoding each job on its own,
+for any launch shape.
 """
 import numpy as np
 import pytest
@@ -57,7 +58,12 @@ def _same(a, b, tag):
 
 @pytest.mark.parametrize("tuning", [dict(), dict(check_steps_per_wave=1), dict(check_steps_per_wave=2),
                                     dict(stagger=False), dict(graph=False), dict(blocks_per_cu=1),
-                                    dict(interleave=32), dict(interleave=16), dict(interleave=16, graph=False)])
+                                    dict(interleave=32), dict(interleave=16), dict(interleave=16, graph=False),
+                                    dict(phase_launches=True), dict(phase_launches=True, stagger=False),
+                                    dict(phase_launches=True, check_steps_per_wave=2),
+                                    dict(phase_launches=True, check_steps_per_wave=1, graph=False),
+                                    dict(phase_launches=True, interleave=32),
+                                    dict(phase_launches=True, interleave=16, stagger=False)])
 def test_batched_equals_plain_decode(mix, tuning):
     jobs = [j for j, _ in mix]
     print("batched", tuning, flush=True)
@@ -181,12 +187,14 @@ def test_graph_cache_does_not_outlive_a_freed_code():
         code.close()
 
 
-def test_batched_against_the_oracle_at_waterfall_snrs():
-    """One persistent launch of three jobs (one per rate, waterfall SNRs, budgets
-    60 / 90 / 120) against the FP64 oracle directly: converged flags are the
-    exact syndrome test of the decoded bits, and every frame's word, flag and
-    count (within one iteration) equal the oracle's, except frames on which the
-    oracle's own outcome moves under 1e-7 perturbations of the inputs (listed)."""
+@pytest.mark.parametrize("phase_launches", [False, True])
+def test_batched_against_the_oracle_at_waterfall_snrs(phase_launches):
+    """One batched launch of three jobs (one per rate, waterfall SNRs, budgets
+    60 / 90 / 120; persistent or one launch per phase) against the FP64 oracle
+    directly: converged flags are the exact syndrome test of the decoded bits,
+    and every frame's word and count (within one iteration) equal the oracle's,
+    except where tests/oracle_outcome.py shows the oracle's own outcome to move
+    under FP32-sized perturbations (listed)."""
     from oracle import code as oc
     from tests import oracle_outcome as oo
 
@@ -200,8 +208,9 @@ def test_batched_against_the_oracle_at_waterfall_snrs():
         syn = oc.syndrome(code_o, bits)
         jobs.append(met.Job(code, torch.from_numpy(llr).to(DEV), torch.from_numpy(syn).to(DEV), max_iter))
         inputs.append((code_o, llr, syn, max_iter))
-    print("batched vs oracle", [s[:5] for s in specs], flush=True)
-    dec = met.BatchedDecoder()
+    print("batched vs oracle", [s[:5] for s in specs], "phase launches" if phase_launches else "persistent",
+          flush=True)
+    dec = met.BatchedDecoder(phase_launches=phase_launches)
     out = dec(jobs)
     torch.cuda.synchronize()
     assert not dec.barrier_expired()

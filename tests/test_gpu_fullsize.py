@@ -82,8 +82,9 @@ def test_full_size_properties_at_waterfall():
 
 def test_batched_mix_at_full_size_equals_plain():
     """The benchmark's batched launch itself: the three codes at N = 10^6, 64
-    frames each, budgets 100 / 150 / 200, early exit, autotuned launch shape;
-    every job's bits, iteration counts and flags equal the plain decode's."""
+    frames each, budgets 100 / 150 / 200, early exit, autotuned launch shape
+    (and the other schedule); every job's bits, iteration counts and flags
+    equal the plain decode's."""
     jobs = []
     for prof, budget in (("r0.1", 100), ("r0.05", 150), ("r0.02", 200)):
         code = met.Code.build(PROFILES[prof], N, SEED[prof])
@@ -91,14 +92,21 @@ def test_batched_mix_at_full_size_equals_plain():
         syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
         jobs.append(met.Job(code, torch.from_numpy(llr).to(DEV), syn, budget))
     dec = met.BatchedDecoder()
-    print("autotune", dec.autotune(jobs), flush=True)
+    shape = dec.autotune(jobs)
+    print("autotune", shape, flush=True)
     out = dec(jobs)
     ref = [met.decode(j.code, j.llr, j.syn, j.max_iter) for j in jobs]
     torch.cuda.synchronize()
     assert not dec.barrier_expired()
-    for k, (a, b) in enumerate(zip(out, ref)):
-        for x, y in ((a.bits, b.bits), (a.iterations, b.iterations), (a.converged, b.converged)):
-            np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy(), err_msg="job %d" % k)
+    # and the other schedule (persistent launch or one launch per phase)
+    other = met.BatchedDecoder(phase_launches=shape["schedule"] == "persistent")
+    out2 = other(jobs)
+    torch.cuda.synchronize()
+    assert not other.barrier_expired()
+    for got in (out, out2):
+        for k, (a, b) in enumerate(zip(got, ref)):
+            for x, y in ((a.bits, b.bits), (a.iterations, b.iterations), (a.converged, b.converged)):
+                np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy(), err_msg="job %d" % k)
 
 
 def test_weighted_bp_at_full_size():

@@ -225,7 +225,7 @@ def test_batched_argument_validation_without_gpu():
     t.check_steps_per_wave = 3
     assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
     t.check_steps_per_wave = 0
-    t.batch_flags = 4
+    t.batch_flags = 8
     assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
     assert L.met_batched_check(None, None) == -1
 
