@@ -52,7 +52,7 @@ MIX = ("r0.1", "r0.05", "r0.02")
 KERNEL_SOURCES = ("met_gpu.h", "met_decode.hip", "met_batched.hip")
 
 
-def class_bytes_per_frame(cls: dict, W: int, first: bool = False, test: bool = True) -> float:
+def class_bytes_per_frame(cls: dict, W: int, first: bool = False, test: bool = True, cb: int = 4) -> float:
     """Unique bytes one check-kernel launch over a class of checks moves per
     frame and iteration (n checks of nm message and nl leaf edges each):
 
@@ -64,7 +64,8 @@ def class_bytes_per_frame(cls: dict, W: int, first: bool = False, test: bool = T
     write c2v (4 B per message edge) and leaf decisions (1 bit per leaf edge).
     """
     n, nm, nl = cls["n_checks"], cls["n_msg"], cls["n_leaf"]
-    b = (0 if first else 4 * nm * n) + 4 * nm * n + 4 * cls["n_msg_vn_touched"] + 4 * nl * n
+    # (cb: bytes of a stored message: 4, or 2 / 1 with half / 8-bit storage)
+    b = (0 if first else cb * nm * n) + cb * nm * n + 4 * cls["n_msg_vn_touched"] + 4 * nl * n
     b += n / 8 + nl * n / 8 + 4 * nm * n / W
     if test:
         b += nl * n / 8
@@ -76,11 +77,11 @@ def check_bytes_per_frame(classes: list, W: int, first: bool = False, test: bool
     return sum(class_bytes_per_frame(c, W, first, test) for c in classes if c["n_msg"] >= 0)
 
 
-def variable_bytes_per_frame(st: dict, W: int) -> float:
+def variable_bytes_per_frame(st: dict, W: int, cb: int = 4) -> float:
     """read c2v (gathered, 4 B per message edge) and L (4 B per message VN),
     the VN -> edge lists (shared by W frames); write P (4 B per message VN)."""
     e12, n2 = st["n_msg_edges"], st["n_msg_vn"]
-    return 4 * e12 + 8 * n2 + (4 * e12 + 4 * n2) / W
+    return cb * e12 + 8 * n2 + (4 * e12 + 4 * n2) / W
 
 
 def materialised_bytes_per_frame(code) -> float:
@@ -203,7 +204,7 @@ def active_frames(iters, conv, max_iter: int, early: bool):
     return (last_c[None, :] >= ls[:, None]).sum(1), (last_v[None, :] >= ls[:, None]).sum(1)
 
 
-def job_bytes(code, iters, conv, max_iter: int, early: bool, W: int = 64):
+def job_bytes(code, iters, conv, max_iter: int, early: bool, W: int = 64, cb: int = 4):
     """Algorithmic bytes of one decode of a job: (check updates by class name,
     variable updates)."""
     classes = [c for c in code.classes() if c["n_msg"] >= 0]
@@ -214,9 +215,9 @@ def job_bytes(code, iters, conv, max_iter: int, early: bool, W: int = 64):
         name = "k_check<%d,%d>" % (c["n_msg"], c["n_leaf"])
         b = 0.0
         for l in range(1, max_iter + 1):
-            b += fc[l - 1] * class_bytes_per_frame(c, W, first=(l == 1), test=(early and l >= 2))
+            b += fc[l - 1] * class_bytes_per_frame(c, W, first=(l == 1), test=(early and l >= 2), cb=cb)
         per_class[name] = per_class.get(name, 0.0) + b
-    var = float(fv.sum()) * variable_bytes_per_frame(st, W)
+    var = float(fv.sum()) * variable_bytes_per_frame(st, W, cb)
     return per_class, var
 
 
@@ -478,13 +479,16 @@ def run_single(args, cpu) -> dict:
     d_llr = torch.from_numpy(llr).to(dev)
     d_syn = met.syndrome(code, torch.from_numpy(bits).to(dev))
     half = args.c2v_fp16
-    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters, c2v_fp16=half) + 256, dtype=torch.uint8,
+    q8 = args.c2v_q8
+    ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters, c2v_fp16=half, c2v_q8=q8) + 256,
+                     dtype=torch.uint8,
                      device=dev)
     torch.cuda.synchronize()
 
     def step():
         return met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
-                          check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk, c2v_fp16=half)
+                          check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk, c2v_fp16=half,
+                          c2v_q8=q8)
 
     ms_ev, kt, out = timed(step, args.steps, args.warmup)
     # throughput from a pass without the per-launch events (they cost the
@@ -493,7 +497,8 @@ def run_single(args, cpu) -> dict:
     value = B * n * args.steps / (ms * 1e-3) / 1e6
     W = 1 if B <= 1 else 4 if B <= 4 else 16 if B <= 16 else 32 if B <= 32 else 64
     early = not args.fixed_iters
-    cls, var = job_bytes(code, out.iterations.cpu().numpy(), out.converged.cpu().numpy(), max_iter, early, W)
+    cls, var = job_bytes(code, out.iterations.cpu().numpy(), out.converged.cpu().numpy(), max_iter, early, W,
+                         cb=2 if half else 1 if q8 else 4)
     classes = [c for c in code.classes() if c["n_msg"] >= 0]
     dom = max(classes, key=lambda c: c["n_checks"] * (c["n_msg"] + c["n_leaf"]))
     kname = "k_check<%d,%d>" % (dom["n_msg"], dom["n_leaf"])
@@ -517,8 +522,8 @@ def run_single(args, cpu) -> dict:
     # per iteration of the slowest frame (small cases are launch-bound: this,
     # not the roofline, is their figure)
     rec["us_per_iteration"] = round(1e3 * ms / args.steps / max(1, int(out.iterations.max().item())), 2)
-    if half:  # the batched form stores float messages only
-        rec["config"]["c2v_storage"] = "fp16"
+    if half or q8:  # the batched form stores float messages only
+        rec["config"]["c2v_storage"] = "fp16" if half else "8-bit log-magnitude codes"
         return rec
     # the same job through the batched persistent launch (one graph replay per
     # decode), on the same inputs; outputs must be identical
@@ -848,6 +853,8 @@ def main() -> int:
     ap.add_argument("--fixed-iters", action="store_true")
     ap.add_argument("--c2v-fp16", action="store_true",
                     help="single: check-to-variable messages stored in half precision (MET_C2V_FP16)")
+    ap.add_argument("--c2v-q8", action="store_true",
+                    help="single: check-to-variable messages stored in 8 bits (MET_C2V_Q8)")
     ap.add_argument("--waterfall", action="store_true",
                     help="jobs at the waterfall SNRs of their rates (0.19 / 0.10 / 0.065) instead of the "
                          "workload's operating points")

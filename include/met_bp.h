@@ -67,6 +67,14 @@ extern "C" {
                                those of the float decoder; its gate is the
                                frame error rate (within the 95 % interval of
                                the float decoder's on the same frames) */
+#define MET_C2V_Q8 16u      /* check-to-variable messages stored in 8 bits:
+                               sign and a 7-bit index into a log-uniform grid
+                               of magnitudes (0, then 2^-14 to 2^5 in 126
+                               steps, 5.4 % rounding at most), read back
+                               through a 128-entry table; all arithmetic in
+                               float.  A quarter of the message bytes.  Groups
+                               of 64 frames only (B > 32), no compaction.
+                               Gated like MET_C2V_FP16 by the frame error rate */
 #define MET_NO_DEG1_SKIP 4u /* degree-1 variable nodes take part in every
                                iteration like the others (their check messages
                                are stored and their posteriors updated; the
@@ -237,7 +245,7 @@ int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int
  *   syn:       dev uint8   [B][M]
  *   max_iter:  >= 1
  *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS, optionally | MET_NO_COMPACT,
- *              | MET_NO_DEG1_SKIP and/or | MET_C2V_FP16
+ *              | MET_NO_DEG1_SKIP and/or | MET_C2V_FP16 or | MET_C2V_Q8
  *   bits:      dev uint8 [B][N] output, hard decisions at each frame's stop
  *   iters:     dev int32 [B] output, iterations run (1..max_iter)
  *   converged: dev uint8 [B] output, 1 iff H bits = syn

@@ -6,7 +6,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import (MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER, MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
+from ._lib import (MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER, MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_C2V_Q8, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
                    met_check_class,
                    met_code_stats, met_job, met_kernel_time, met_profile, met_tuning)
 
@@ -184,10 +184,10 @@ def mdr_alice(x, alpha, ynorm, sigma_z2: float, d: int = 8, stream=None):
 
 
 def workspace_bytes(code: Code, frames: int, fixed_iters: bool = False, posterior: bool = False,
-                    deg1_skip: bool = True, c2v_fp16: bool = False) -> int:
+                    deg1_skip: bool = True, c2v_fp16: bool = False, c2v_q8: bool = False) -> int:
     n = ctypes.c_size_t()
     flags = ((MET_FIXED_ITERS if fixed_iters else 0) | (0 if deg1_skip else MET_NO_DEG1_SKIP)
-             | (MET_C2V_FP16 if c2v_fp16 else 0))
+             | (MET_C2V_FP16 if c2v_fp16 else 0) | (MET_C2V_Q8 if c2v_q8 else 0))
     check(lib.met_decode_workspace_bytes(code.handle, int(frames), flags, int(bool(posterior)), ctypes.byref(n)))
     return int(n.value)
 
@@ -202,7 +202,8 @@ class DecodeOutput:
 
 def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, posterior: bool = False,
            workspace=None, stream=None, check_steps_per_wave: int = 0, variable_chunk: int = 0,
-           compact: bool = True, deg1_skip: bool = True, c2v_fp16: bool = False) -> DecodeOutput:
+           compact: bool = True, deg1_skip: bool = True, c2v_fp16: bool = False,
+           c2v_q8: bool = False) -> DecodeOutput:
     """Decode llr float32 [B, N] against syn uint8 [B, M] (device tensors).
 
     check_steps_per_wave and variable_chunk (0 = default) select launch shapes
@@ -210,14 +211,15 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
     their groups; results do not depend on any of them.  deg1_skip=False
     iterates degree-1 variable nodes like the others (MET_NO_DEG1_SKIP; equal
     results up to FP32 rounding).  c2v_fp16=True stores check-to-variable
-    messages in half precision (MET_C2V_FP16; more than 32 frames)."""
+    messages in half precision (MET_C2V_FP16; more than 32 frames), c2v_q8=True
+    in 8 bits (MET_C2V_Q8; more than 32 frames)."""
     import torch
 
     b = int(llr.shape[0])
     dev = llr.device
     _require(llr, torch.float32, (b, code.N), "llr")
     _require(syn, torch.uint8, (b, code.M), "syn")
-    need = workspace_bytes(code, b, fixed_iters, posterior, deg1_skip, c2v_fp16)
+    need = workspace_bytes(code, b, fixed_iters, posterior, deg1_skip, c2v_fp16, c2v_q8)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     off = (-workspace.data_ptr()) % 256
@@ -234,7 +236,8 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
         lib.met_decode_ex(
             code.handle, llr.data_ptr(), syn.data_ptr(), b, int(max_iter),
             (MET_FIXED_ITERS if fixed_iters else 0) | (0 if compact else MET_NO_COMPACT)
-            | (0 if deg1_skip else MET_NO_DEG1_SKIP) | (MET_C2V_FP16 if c2v_fp16 else 0),
+            | (0 if deg1_skip else MET_NO_DEG1_SKIP) | (MET_C2V_FP16 if c2v_fp16 else 0)
+            | (MET_C2V_Q8 if c2v_q8 else 0),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(),
             None if post is None else post.data_ptr(),
             ctypes.c_void_p(ws_ptr), ws_len, ctypes.byref(tuning), _stream_ptr(stream),

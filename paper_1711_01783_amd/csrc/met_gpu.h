@@ -68,6 +68,65 @@ constexpr int kXcds = 8;  // accelerator dies; the hardware deals block b to die
 // converted to float on load and rounded to nearest on store; the arithmetic
 // is float either way.
 using half_t = _Float16;
+
+// 8-bit storage (MET_C2V_Q8): sign in bit 7 and the magnitude as an index k
+// into a log-uniform grid, k = 0 for 0 and m_k = 2^(kQ8Lo + (k - 1) / kQ8PerOctave)
+// for k = 1..127 (2^-14 to 2^5: magnitudes are at most about 30 after the
+// clamp, and below 2^-14 a message moves no posterior that matters).  Codes
+// are formed by rounding log2|v| on that grid (the geometric midpoints are the
+// thresholds: relative error at most 2^(1/(2 kQ8PerOctave)) - 1 = 5.4 %) and
+// read back through a 128-entry table of the grid values.
+constexpr float kQ8Lo = -14.0f, kQ8Hi = 5.0f;
+constexpr float kQ8PerOctave = 126.0f / (kQ8Hi - kQ8Lo);
+__device__ __forceinline__ uint32_t q8_encode(float v) {
+  float t = fmaf(__builtin_amdgcn_logf(fabsf(v)) - kQ8Lo, kQ8PerOctave, 1.0f);  // log2 on the grid
+  t = fminf(fmaxf(__builtin_rintf(t), 0.0f), 127.0f);  // 0 and NaN give code 0
+  return (uint32_t)t | ((__float_as_uint(v) >> 24) & 128u);
+}
+struct q8_t {
+  uint8_t c;
+  q8_t() = default;
+  __device__ explicit q8_t(float v) : c((uint8_t)q8_encode(v)) {}
+  __device__ operator float() const;
+};
+// The decoding table, built at compile time: 2^x as 2^n e^(f ln 2), the
+// exponential by its Taylor series in double (f ln 2 < 0.7: 24 terms leave no
+// error in double), rounded once to float.
+struct Q8Table {
+  float v[128];
+};
+constexpr double q8_exp2(double x) {
+  int n = 0;
+  while (x < 0.0) {
+    x += 1.0;
+    --n;
+  }
+  while (x >= 1.0) {
+    x -= 1.0;
+    ++n;
+  }
+  const double y = x * 0.69314718055994530942;
+  double term = 1.0, sum = 1.0;
+  for (int i = 1; i < 24; ++i) {
+    term *= y / i;
+    sum += term;
+  }
+  for (; n > 0; --n) sum *= 2.0;
+  for (; n < 0; ++n) sum *= 0.5;
+  return sum;
+}
+constexpr Q8Table make_q8_table() {
+  Q8Table t{};
+  t.v[0] = 0.0f;
+  for (int k = 1; k < 128; ++k) t.v[k] = (float)q8_exp2((double)kQ8Lo + (double)(k - 1) / (double)kQ8PerOctave);
+  return t;
+}
+[[maybe_unused]] static __constant__ Q8Table kQ8Table = make_q8_table();
+__device__ __forceinline__ q8_t::operator float() const {
+  const float m = kQ8Table.v[c & 127u];
+  return (c & 128u) ? -m : m;
+}
+
 template <typename CT>
 __device__ __forceinline__ float ld_c2v(const float *base, int64_t i) {
   return (float)reinterpret_cast<const CT *>(base)[i];
@@ -893,12 +952,12 @@ void launch_fixed_ipw(int ipw, int shape, unsigned blocks, int G, hipStream_t st
 }
 
 // One check-kernel launch over a class: compiled shape (mode, steps per wave)
-// or the run-time-degree kernel.  Half-precision message storage is compiled
-// for groups of 64 frames with 4 check steps per wave only.
+// or the run-time-degree kernel.  Half-precision and 8-bit message storage are
+// compiled for groups of 64 frames with 4 check steps per wave only.
 template <int W, typename CT = float>
 void launch_check(const CheckParams &p, const ClassArgs &a, int mode, int cn_ipw, int G, hipStream_t st) {
-  constexpr bool half = std::is_same<CT, half_t>::value;
-  static_assert(!half || W == 64, "half-precision messages need groups of 64 frames");
+  constexpr bool half = !std::is_same<CT, float>::value;  // half or 8-bit storage
+  static_assert(!half || W == 64, "reduced message storage needs groups of 64 frames");
   const bool gen = a.shape == kShapeGeneric;
   const int ipw = (W == 64 && !gen) ? (half ? 4 : cn_ipw) : 1;
   const int64_t per_block = (int64_t)kWavesPerBlock * ipw * (64 / W);

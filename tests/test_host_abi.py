@@ -305,3 +305,16 @@ def test_peg_validation():
         met.Code.build_peg(PROFILES["r0.1"], 4096, 1, [0, 1, 1])
     with pytest.raises(met.MetError, match="depth"):
         met.Code.build_peg(PROFILES["r0.1"], 4096, 1, [17, 1, 1])
+
+
+def test_q8_messages_flag():
+    c = met.Code.build(PROFILES["r0.1"], 4096, 1)
+    L = _lib.lib
+    n = ctypes.c_size_t()
+    assert L.met_decode_workspace_bytes(c.handle, 64, _lib.MET_C2V_Q8, 0, ctypes.byref(n)) == 0
+    q8 = n.value
+    assert L.met_decode_workspace_bytes(c.handle, 64, _lib.MET_C2V_FP16, 0, ctypes.byref(n)) == 0
+    assert q8 < n.value
+    assert L.met_decode_workspace_bytes(c.handle, 20, _lib.MET_C2V_Q8, 0, ctypes.byref(n)) == -1   # W < 64
+    assert L.met_decode_workspace_bytes(c.handle, 64, _lib.MET_C2V_Q8 | _lib.MET_C2V_FP16, 0,
+                                        ctypes.byref(n)) == -1
