@@ -122,7 +122,7 @@ def test_decode_argument_validation_without_gpu():
     dummy = P(256)
     n = ctypes.c_size_t()
     assert L.met_decode_workspace_bytes(c.handle, 0, 0, 0, ctypes.byref(n)) == -1
-    assert L.met_decode_workspace_bytes(c.handle, 64, 16, 0, ctypes.byref(n)) == -1
+    assert L.met_decode_workspace_bytes(c.handle, 64, 32, 0, ctypes.byref(n)) == -1
     assert L.met_decode_workspace_bytes(None, 64, 0, 0, ctypes.byref(n)) == -1
     assert L.met_decode_workspace_bytes(c.handle, 64, 0, 0, ctypes.byref(n)) == 0 and n.value > 0
     big = n.value
@@ -140,7 +140,7 @@ def test_decode_argument_validation_without_gpu():
     assert call(llr=P(258)) == -1          # misaligned float buffer
     assert call(ws=P(264)) == -1           # workspace not 256-byte aligned
     assert call(wsb=big - 1) == -1         # too small
-    assert call(flags=16) == -1
+    assert call(flags=32) == -1
     assert "flags" in L.met_last_error().decode()
     assert call(flags=4) == -1             # the all-VN layout needs a larger workspace
     assert "workspace" in L.met_last_error().decode()
