@@ -170,7 +170,7 @@ __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) 
   p.unsat = unsat + (size_t)((l - 1) & 1) * G;
   p.unsat_clear = c == 0 ? unsat + (size_t)(l & 1) * G : nullptr;
   const ClassArgs a = jobs[j].cls[c];
-  constexpr int I2 = IPW > 2 ? 2 : IPW;  // degree-11/12 checks: at most 2 steps
+  constexpr int I2 = 1;  // degree-11/12 checks: one step (keeps the union of the shapes' registers small)
   const int gi = (int)g;
   // One compiled mode: c2v starts zero-filled, so iteration 1 needs no variant.
   switch (a.shape) {
@@ -352,7 +352,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
 // the tile claims.  Blocks are short-lived, so the hardware's preference for
 // older waves rotates over the blocks instead of fixing the order of the
 // resident ones for a whole phase.
-template <int IPW, bool GEN, int W>
+// KIND 1 / 2: a phase holding only check / only variable tiles (every phase
+// when the jobs are not staggered), compiled without the other body so that
+// its register budget is its own; KIND 0 holds both.
+template <int IPW, bool GEN, int W, int KIND>
 __global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_jobs, int phase) {
   CJob *jobs = (CJob *)table;
   int64_t t = blockIdx.x;
@@ -360,10 +363,11 @@ __global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_j
     int l = 0, kind = 0;
     const int64_t cnt = job_tiles(jobs, j, phase, &l, &kind);
     if (t < cnt) {
-      if (kind == 0)
-        check_tile<IPW, GEN, W>(jobs, j, l, t);
-      else
-        variable_tile<W>(jobs, j, l, t);
+      if (kind == 0) {
+        if constexpr (KIND != 2) check_tile<IPW, GEN, W>(jobs, j, l, t);
+      } else {
+        if constexpr (KIND != 1) variable_tile<W>(jobs, j, l, t);
+      }
       return;
     }
     t -= cnt;
@@ -452,12 +456,18 @@ struct Batched {
   unsigned grid = 0;
   bool gen = false;  // some class has no compiled shape
 
-  const void *phase_kernel() const {
-    if (W == 32) return gen ? (const void *)k_phase<1, true, 32> : (const void *)k_phase<1, false, 32>;
-    if (W == 16) return gen ? (const void *)k_phase<1, true, 16> : (const void *)k_phase<1, false, 16>;
-    if (gen) return (const void *)k_phase<1, true, 64>;
-    return ipw == 4 ? (const void *)k_phase<4, false, 64>
-                    : ipw == 2 ? (const void *)k_phase<2, false, 64> : (const void *)k_phase<1, false, 64>;
+  template <int KIND>
+  const void *phase_kernel_k() const {
+    if (W == 32) return gen ? (const void *)k_phase<1, true, 32, KIND> : (const void *)k_phase<1, false, 32, KIND>;
+    if (W == 16) return gen ? (const void *)k_phase<1, true, 16, KIND> : (const void *)k_phase<1, false, 16, KIND>;
+    if (gen) return (const void *)k_phase<1, true, 64, KIND>;
+    return ipw == 4 ? (const void *)k_phase<4, false, 64, KIND>
+                    : ipw == 2 ? (const void *)k_phase<2, false, 64, KIND> : (const void *)k_phase<1, false, 64, KIND>;
+  }
+  const void *phase_kernel(bool checks, bool variables) const {
+    if (checks && !variables) return phase_kernel_k<1>();
+    if (variables && !checks) return phase_kernel_k<2>();
+    return phase_kernel_k<0>();
   }
 
   const void *kernel() const {
@@ -617,19 +627,22 @@ struct Batched {
     const BatchJob *tab = reinterpret_cast<const BatchJob *>(ws + L.off_table);
     hipLaunchKernelGGL(k_control_init, dim3(1), dim3(kBlock), 0, st, reinterpret_cast<uint32_t *>(ctl));
     if (phases) {
-      const void *kp = phase_kernel();
       for (int ph = 0; ph < n_phases; ++ph) {
         int64_t tiles = 0;
+        bool checks = false, variables = false;
         for (int j = 0; j < n; ++j) {
           const BatchJob &b = table[j];
           const int s = ph - b.offset;
-          if (s >= 0 && s < 2 * b.max_iter) tiles += (int64_t)((s & 1) == 0 ? b.cn_tiles : b.vn_blocks) * b.G;
+          if (s < 0 || s >= 2 * b.max_iter) continue;
+          const int64_t c = (int64_t)((s & 1) == 0 ? b.cn_tiles : b.vn_blocks) * b.G;
+          if (c > 0) ((s & 1) == 0 ? checks : variables) = true;
+          tiles += c;
         }
         if (tiles == 0) continue;
         ScopedTimer t(st, "k_phase");
         int phv = ph;
         void *args[] = {(void *)&tab, (void *)&n, (void *)&phv};
-        (void)hipLaunchKernel(kp, dim3((unsigned)tiles), dim3(kBlock), args, 0, st);
+        (void)hipLaunchKernel(phase_kernel(checks, variables), dim3((unsigned)tiles), dim3(kBlock), args, 0, st);
       }
     } else {
       ScopedTimer t(st, "k_persistent");
