@@ -42,6 +42,8 @@ struct BatchJob {
   VarParams vp;
   ClassArgs cls[kMaxClasses];
   int32_t cls_blocks[kMaxClasses];  // tiles of each class per frame group
+  int32_t cls_wide[kMaxClasses];    // 1 for classes outside the (3,1) / (2,1) shapes
+  int32_t cn_tiles_k[2];            // tiles per frame group of narrow / wide classes
   int32_t n_classes, cn_tiles, vn_blocks, G;
   int32_t max_iter, early, offset, pad;
   float *P, *L2;
@@ -150,14 +152,26 @@ using CJob = const __attribute__((address_space(4))) BatchJob;
 using CJob = const BatchJob;  // the host pass only parses device code
 #endif
 
-// Check tile t of job j at iteration l.
-template <int IPW, bool GEN, int W>
+// Check tile t of job j at iteration l, among all of its check tiles (KF = -1)
+// or among the tiles of its narrow (KF = 0: the (3,1) and (2,1) shapes) or
+// wide (KF = 1: every other shape) classes.
+// PERSIST: inside the persistent launch (words written by earlier phases of the
+// same launch are read with vector loads); false in the phase launches, where
+// every earlier phase is an earlier launch and such words are constant.
+template <int IPW, bool GEN, int W, int KF = -1, bool PERSIST = true>
 __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) {
-  const int32_t cn_tiles = jobs[j].cn_tiles;
+  const int32_t cn_tiles = KF < 0 ? jobs[j].cn_tiles : jobs[j].cn_tiles_k[KF < 0 ? 0 : KF];
   const int64_t g = t / cn_tiles;
   int64_t r = t % cn_tiles;
   int c = 0;
-  while (r >= jobs[j].cls_blocks[c]) r -= jobs[j].cls_blocks[c++];
+  if constexpr (KF < 0) {
+    while (r >= jobs[j].cls_blocks[c]) r -= jobs[j].cls_blocks[c++];
+  } else {
+    while (jobs[j].cls_wide[c] != KF || r >= jobs[j].cls_blocks[c]) {
+      if (jobs[j].cls_wide[c] == KF) r -= jobs[j].cls_blocks[c];
+      ++c;
+    }
+  }
   CheckParams p = jobs[j].cp;
   const int64_t lw = jobs[j].leaf_words;
   uint64_t *B1 = jobs[j].B1, *unsat = jobs[j].unsat;
@@ -173,28 +187,29 @@ __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) 
   constexpr int I2 = 1;  // degree-11/12 checks: one step (keeps the union of the shapes' registers small)
   const int gi = (int)g;
   // One compiled mode: c2v starts zero-filled, so iteration 1 needs no variant.
+  constexpr bool narrow = KF != 1, wide = KF != 0;
   switch (a.shape) {
-    case 0: check_fixed_body<W, 3, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 1: check_fixed_body<W, 2, 1, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 2: check_fixed_body<W, 12, 0, M_MAIN, I2, true>(p, a, r, gi); break;
-    case 3: check_fixed_body<W, 11, 0, M_MAIN, I2, true>(p, a, r, gi); break;
-    case 4: check_fixed_body<W, 6, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 5: check_fixed_body<W, 5, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
-    case 6: check_fixed_body<W, 4, 0, M_MAIN, IPW, true>(p, a, r, gi); break;
+    case 0: if constexpr (narrow) check_fixed_body<W, 3, 1, M_MAIN, IPW, PERSIST>(p, a, r, gi); break;
+    case 1: if constexpr (narrow) check_fixed_body<W, 2, 1, M_MAIN, IPW, PERSIST>(p, a, r, gi); break;
+    case 2: if constexpr (wide) check_fixed_body<W, 12, 0, M_MAIN, I2, PERSIST>(p, a, r, gi); break;
+    case 3: if constexpr (wide) check_fixed_body<W, 11, 0, M_MAIN, I2, PERSIST>(p, a, r, gi); break;
+    case 4: if constexpr (wide) check_fixed_body<W, 6, 0, M_MAIN, IPW, PERSIST>(p, a, r, gi); break;
+    case 5: if constexpr (wide) check_fixed_body<W, 5, 0, M_MAIN, IPW, PERSIST>(p, a, r, gi); break;
+    case 6: if constexpr (wide) check_fixed_body<W, 4, 0, M_MAIN, IPW, PERSIST>(p, a, r, gi); break;
     default:
-      if (GEN) check_generic_body<W, true>(p, a, r, gi);
+      if constexpr (wide && GEN) check_generic_body<W, PERSIST>(p, a, r, gi);
       break;
   }
 }
 
-template <int W>
+template <int W, bool PERSIST = true>
 __device__ __forceinline__ void variable_tile(CJob *jobs, int j, int l, int64_t t) {
   VarParams vp = jobs[j].vp;
   const int32_t vb = jobs[j].vn_blocks;
   vp.it = l;
   vp.retire = jobs[j].early && l >= 2;
   vp.unsat = jobs[j].unsat + (size_t)((l - 1) & 1) * jobs[j].G;
-  variable_body<W, 16, true>(vp, t % vb, (int)(t / vb));
+  variable_body<W, 16, PERSIST>(vp, t % vb, (int)(t / vb));
 }
 
 // Phase step of job j: s = phase - offset; even s: check update of iteration
@@ -352,21 +367,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
 // the tile claims.  Blocks are short-lived, so the hardware's preference for
 // older waves rotates over the blocks instead of fixing the order of the
 // resident ones for a whole phase.
-// KIND 1 / 2: a phase holding only check / only variable tiles (every phase
-// when the jobs are not staggered), compiled without the other body so that
-// its register budget is its own; KIND 0 holds both.
+// KIND 0 holds every tile of the phase (check and variable tiles when the jobs
+// are staggered); without stagger a phase holds one kind, run as up to two
+// launches each compiled without the other bodies, so that every launch has
+// its own register budget: KIND 1 the check tiles of the (3,1) / (2,1) shapes
+// (the bulk of the work, as lean as the plain decoder's check kernel), KIND 3
+// the check tiles of every other shape, KIND 2 the variable tiles.
 template <int IPW, bool GEN, int W, int KIND>
 __global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_jobs, int phase) {
   CJob *jobs = (CJob *)table;
   int64_t t = blockIdx.x;
   for (int j = 0; j < n_jobs; ++j) {
     int l = 0, kind = 0;
-    const int64_t cnt = job_tiles(jobs, j, phase, &l, &kind);
+    int64_t cnt = job_tiles(jobs, j, phase, &l, &kind);
+    if constexpr (KIND == 1 || KIND == 3) cnt = kind == 0 ? (int64_t)jobs[j].cn_tiles_k[KIND == 3] * jobs[j].G : 0;
+    if constexpr (KIND == 2) cnt = kind == 1 ? cnt : 0;
     if (t < cnt) {
-      if (kind == 0) {
-        if constexpr (KIND != 2) check_tile<IPW, GEN, W>(jobs, j, l, t);
+      if constexpr (KIND == 0) {
+        if (kind == 0)
+          check_tile<IPW, GEN, W, -1, false>(jobs, j, l, t);
+        else
+          variable_tile<W, false>(jobs, j, l, t);
+      } else if constexpr (KIND == 1) {
+        check_tile<IPW, false, W, 0, false>(jobs, j, l, t);
+      } else if constexpr (KIND == 3) {
+        check_tile<IPW, GEN, W, 1, false>(jobs, j, l, t);
       } else {
-        if constexpr (KIND != 1) variable_tile<W>(jobs, j, l, t);
+        variable_tile<W, false>(jobs, j, l, t);
       }
       return;
     }
@@ -410,7 +437,7 @@ BatchLayout make_batch_layout(const met_job *jobs, int n, int W) {
 
 int shape_ipw(int shape, int ipw) {
   if (shape == kShapeGeneric) return 1;
-  if (kShapeMsg[shape] >= 11) return std::min(ipw, 2);
+  if (kShapeMsg[shape] >= 11) return 1;  // as check_tile compiles them
   return ipw;
 }
 
@@ -464,10 +491,13 @@ struct Batched {
     return ipw == 4 ? (const void *)k_phase<4, false, 64, KIND>
                     : ipw == 2 ? (const void *)k_phase<2, false, 64, KIND> : (const void *)k_phase<1, false, 64, KIND>;
   }
-  const void *phase_kernel(bool checks, bool variables) const {
-    if (checks && !variables) return phase_kernel_k<1>();
-    if (variables && !checks) return phase_kernel_k<2>();
-    return phase_kernel_k<0>();
+  const void *phase_kernel(int kind) const {
+    switch (kind) {
+      case 1: return phase_kernel_k<1>();
+      case 2: return phase_kernel_k<2>();
+      case 3: return phase_kernel_k<3>();
+      default: return phase_kernel_k<0>();
+    }
   }
 
   const void *kernel() const {
@@ -547,12 +577,15 @@ struct Batched {
     for (int j = 0; j < n; ++j) {
       BatchJob &b = table[j];
       b.cn_tiles = 0;
+      b.cn_tiles_k[0] = b.cn_tiles_k[1] = 0;
       for (int k = 0; k < b.n_classes; ++k) {
         const ClassArgs &ck = b.cls[k];
         const int ip = shape_ipw(ck.shape, ipw);
         const int64_t per = (int64_t)kWavesPerBlock * ip * (64 / W);  // checks per tile
         b.cls_blocks[k] = (int32_t)((ck.n_checks + per - 1) / per);
         b.cn_tiles += b.cls_blocks[k];
+        b.cls_wide[k] = (ck.shape == 0 || ck.shape == 1) ? 0 : 1;
+        b.cn_tiles_k[b.cls_wide[k]] += b.cls_blocks[k];
       }
     }
     n_phases = max_end;
@@ -628,21 +661,29 @@ struct Batched {
     hipLaunchKernelGGL(k_control_init, dim3(1), dim3(kBlock), 0, st, reinterpret_cast<uint32_t *>(ctl));
     if (phases) {
       for (int ph = 0; ph < n_phases; ++ph) {
-        int64_t tiles = 0;
-        bool checks = false, variables = false;
+        // tiles of the phase: [0] all, [1] narrow checks, [2] variables, [3] wide checks
+        int64_t tiles[4] = {0, 0, 0, 0};
         for (int j = 0; j < n; ++j) {
           const BatchJob &b = table[j];
           const int s = ph - b.offset;
           if (s < 0 || s >= 2 * b.max_iter) continue;
-          const int64_t c = (int64_t)((s & 1) == 0 ? b.cn_tiles : b.vn_blocks) * b.G;
-          if (c > 0) ((s & 1) == 0 ? checks : variables) = true;
-          tiles += c;
+          if ((s & 1) == 0) {
+            tiles[1] += (int64_t)b.cn_tiles_k[0] * b.G;
+            tiles[3] += (int64_t)b.cn_tiles_k[1] * b.G;
+          } else {
+            tiles[2] += (int64_t)b.vn_blocks * b.G;
+          }
         }
-        if (tiles == 0) continue;
-        ScopedTimer t(st, "k_phase");
+        tiles[0] = tiles[1] + tiles[2] + tiles[3];
+        if (tiles[0] == 0) continue;
         int phv = ph;
         void *args[] = {(void *)&tab, (void *)&n, (void *)&phv};
-        (void)hipLaunchKernel(phase_kernel(checks, variables), dim3((unsigned)tiles), dim3(kBlock), args, 0, st);
+        const bool mixed = tiles[2] > 0 && tiles[1] + tiles[3] > 0;
+        for (int kind : {0, 1, 3, 2}) {
+          if (mixed ? kind != 0 : (kind == 0 || tiles[kind] == 0)) continue;
+          ScopedTimer t(st, "k_phase");
+          (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)tiles[kind]), dim3(kBlock), args, 0, st);
+        }
       }
     } else {
       ScopedTimer t(st, "k_persistent");
@@ -707,6 +748,7 @@ struct Batched {
     append_bytes(k, dev);
     append_bytes(k, ipw);
     append_bytes(k, phases);
+    append_bytes(k, stagger);  // the phase schedule bakes each phase's tile count into the graph
     append_bytes(k, W);
     append_bytes(k, gen);
     append_bytes(k, grid);
