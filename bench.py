@@ -372,9 +372,10 @@ def run_mix(args, cpu) -> dict:
     p_ms_ev, p_kt, p_out = timed(plain, args.steps, args.warmup)
     p_ms = timed_plain(plain, args.steps)
     del wss
-    dec = met.BatchedDecoder(check_steps_per_wave=args.check_steps, blocks_per_cu=args.blocks_per_cu)
+    dec = met.BatchedDecoder(check_steps_per_wave=args.check_steps, blocks_per_cu=args.blocks_per_cu,
+                             phase_launches=args.schedule == "phase", stagger=not args.no_stagger)
     shape = None
-    if not args.no_autotune and not args.check_steps and not args.blocks_per_cu:
+    if args.schedule == "auto" and not args.no_autotune and not args.check_steps and not args.blocks_per_cu:
         shape = dec.autotune(jobs)  # outside the timed region
     b_ms, b_kt, b_out = timed(lambda: dec(jobs), args.steps, args.warmup)
     expired = dec.barrier_expired()
@@ -438,6 +439,7 @@ def run_mix(args, cpu) -> dict:
                "fixed iterations" if args.fixed_iters else "per-frame early exit"),
             "N": n, "frames_per_job": B, "profiles": list(MIX), "code_seeds": [CODE_SEED[p] for p in MIX],
             "frame_seed": FRAME_SEED, "mode": "batched", "schedule": sched,
+            "stagger": not (dec.tuning.batch_flags & 1),
             "interleave": int((shape or {}).get("interleave") or 64),
         },
         "roofline": roof,
@@ -862,6 +864,10 @@ def main() -> int:
     ap.add_argument("--vn-chunk", type=int, default=0, help="variable-kernel gathers in flight (0 = default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")
     ap.add_argument("--no-autotune", action="store_true", help="mix: keep the default persistent launch shape")
+    ap.add_argument("--schedule", default="auto", choices=("auto", "phase", "persistent"),
+                    help="mix: batched schedule (auto = autotuned; phase = one launch per phase, persistent = one "
+                         "persistent launch, both with the default shape)")
+    ap.add_argument("--no-stagger", action="store_true", help="mix: all jobs start in the same phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=50, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
