@@ -347,7 +347,9 @@ typedef struct {
   int32_t variable_chunk;       /* 8, 16 or 32: message gathers the variable
                                    kernel keeps in flight; default 16 */
   int32_t blocks_per_cu;        /* batched: resident blocks per compute unit
-                                   (0 = as many as fit) */
+                                   of the persistent launch (0 = as many as
+                                   fit; unused by phase launches, where the
+                                   autotuner reports 0) */
   uint32_t batch_flags;         /* batched: MET_BATCH_* */
   int32_t interleave;           /* batched: frames per group, 16, 32 or 64
                                    (one check step per wave below 64);

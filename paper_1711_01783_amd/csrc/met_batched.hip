@@ -379,8 +379,9 @@ __global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_j
   int64_t t = blockIdx.x;
   for (int j = 0; j < n_jobs; ++j) {
     int l = 0, kind = 0;
-    int64_t cnt = job_tiles(jobs, j, phase, &l, &kind);
-    if constexpr (KIND == 1 || KIND == 3) cnt = kind == 0 ? (int64_t)jobs[j].cn_tiles_k[KIND == 3] * jobs[j].G : 0;
+    int64_t cnt = job_tiles(jobs, j, phase, &l, &kind);  // 0 (kind unset) outside the job's phases
+    if constexpr (KIND == 1 || KIND == 3)
+      cnt = cnt > 0 && kind == 0 ? (int64_t)jobs[j].cn_tiles_k[KIND == 3] * jobs[j].G : 0;
     if constexpr (KIND == 2) cnt = kind == 1 ? cnt : 0;
     if (t < cnt) {
       if constexpr (KIND == 0) {
