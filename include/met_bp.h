@@ -339,6 +339,21 @@ int met_wbp_backward(const met_code *c, const float *grad_posterior, int32_t B, 
                                    same HIP graph.  Same results.  Launches of
                                    jobs whose frames have all stopped still run
                                    (their tiles return at once) */
+#define MET_BATCH_KIND_STREAMS 8u /* batched, implies MET_BATCH_PHASE_LAUNCHES:
+                                   the launches of one phase (checks of the
+                                   (3,1) / (2,1) shapes, checks of the other
+                                   shapes, variable updates) run on parallel
+                                   streams (graph branches) and join at the
+                                   end of the phase */
+#define MET_BATCH_JOB_STREAMS 16u /* batched, implies MET_BATCH_PHASE_LAUNCHES:
+                                   each job's launches form a chain of their
+                                   own on one of up to 4 parallel streams,
+                                   joined once after the last phase; excludes
+                                   MET_BATCH_KIND_STREAMS.  The parallel modes
+                                   use side streams the library creates per
+                                   device (default priority) and keeps; calls
+                                   that use them must not overlap on one
+                                   device */
 
 typedef struct {
   int32_t check_steps_per_wave; /* 1, 2 or 4: steps of 64/W checks each wave of

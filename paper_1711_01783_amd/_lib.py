@@ -67,6 +67,8 @@ class met_kernel_time(ctypes.Structure):
 MET_BATCH_NO_STAGGER = 1
 MET_BATCH_NO_GRAPH = 2
 MET_BATCH_PHASE_LAUNCHES = 4
+MET_BATCH_KIND_STREAMS = 8
+MET_BATCH_JOB_STREAMS = 16
 
 
 class met_tuning(ctypes.Structure):

@@ -6,7 +6,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import (MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER, MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_C2V_Q8, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
+from ._lib import (MET_BATCH_JOB_STREAMS, MET_BATCH_KIND_STREAMS, MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER,
+                   MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_C2V_Q8, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
                    met_check_class,
                    met_code_stats, met_job, met_kernel_time, met_profile, met_tuning)
 
@@ -316,16 +317,23 @@ class BatchedDecoder:
     Keeps its workspace between calls, so repeated calls with the same jobs
     replay the same cached HIP graph.  check_steps_per_wave / blocks_per_cu /
     stagger / graph / interleave (frames per group: 16, 32 or 64) /
-    phase_launches select launch shapes; results do not depend on them."""
+    phase_launches / streams select launch shapes; results do not depend on
+    them.  streams (phase launches only): "one" (default), "kinds" (the
+    launches of a phase on parallel streams) or "jobs" (each job's launches a
+    chain of their own on parallel streams)."""
+
+    _STREAMS = {"one": 0, "kinds": MET_BATCH_KIND_STREAMS, "jobs": MET_BATCH_JOB_STREAMS}
 
     def __init__(self, check_steps_per_wave: int = 0, blocks_per_cu: int = 0, stagger: bool = True,
-                 graph: bool = True, interleave: int = 0, phase_launches: bool = False):
+                 graph: bool = True, interleave: int = 0, phase_launches: bool = False, streams: str = "one"):
+        if streams not in self._STREAMS:
+            raise ValueError("streams must be one of %s" % sorted(self._STREAMS))
         self.tuning = met_tuning()
         self.tuning.check_steps_per_wave = int(check_steps_per_wave)
         self.tuning.blocks_per_cu = int(blocks_per_cu)
         self.tuning.interleave = int(interleave)
         self.tuning.batch_flags = ((0 if stagger else MET_BATCH_NO_STAGGER) | (0 if graph else MET_BATCH_NO_GRAPH)
-                                   | (MET_BATCH_PHASE_LAUNCHES if phase_launches else 0))
+                                   | (MET_BATCH_PHASE_LAUNCHES if phase_launches else 0) | self._STREAMS[streams])
         self.workspace = None
         self._ws_ptr = 0
 
@@ -380,9 +388,11 @@ class BatchedDecoder:
                                        ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)))
         graph = not (self.tuning.batch_flags & MET_BATCH_NO_GRAPH)
         self.tuning = best
-        self.tuning.batch_flags = ((best.batch_flags & (MET_BATCH_NO_STAGGER | MET_BATCH_PHASE_LAUNCHES))
-                                   | (0 if graph else MET_BATCH_NO_GRAPH))
+        keep = MET_BATCH_NO_STAGGER | MET_BATCH_PHASE_LAUNCHES | MET_BATCH_KIND_STREAMS | MET_BATCH_JOB_STREAMS
+        self.tuning.batch_flags = (best.batch_flags & keep) | (0 if graph else MET_BATCH_NO_GRAPH)
         return {"schedule": "phase launches" if best.batch_flags & MET_BATCH_PHASE_LAUNCHES else "persistent",
+                "streams": ("kinds" if best.batch_flags & MET_BATCH_KIND_STREAMS else
+                            "jobs" if best.batch_flags & MET_BATCH_JOB_STREAMS else "one"),
                 "check_steps_per_wave": int(best.check_steps_per_wave), "blocks_per_cu": int(best.blocks_per_cu),
                 "interleave": int(best.interleave),
                 "stagger": not (best.batch_flags & MET_BATCH_NO_STAGGER), "probe_ms": float(ms.value)}

@@ -465,6 +465,34 @@ int capture_stream(hipStream_t *out) {
   return MET_OK;
 }
 
+// Side streams of the phase schedule's parallel modes (default priority), with
+// the events that fork them from and join them to the launching stream; per
+// device, created on first use and kept until the process ends.
+constexpr int kSideStreams = 3;
+struct SideStreams {
+  hipStream_t s[kSideStreams] = {};
+  hipEvent_t fork = nullptr, join[kSideStreams] = {};
+};
+std::mutex g_side_mu;
+SideStreams g_side[64];
+
+int side_streams(SideStreams **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MET_EHIP, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStreams &ss = g_side[dev];
+  if (!ss.fork) {
+    for (int i = 0; i < kSideStreams; ++i) {
+      if (!ss.s[i]) HIP_TRY(hipStreamCreateWithFlags(&ss.s[i], hipStreamNonBlocking));
+      if (!ss.join[i]) HIP_TRY(hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming));
+  }
+  *out = &ss;
+  return MET_OK;
+}
+
 template <typename T>
 void append_bytes(std::vector<uint8_t> &k, const T &v) {
   const uint8_t *p = reinterpret_cast<const uint8_t *>(&v);
@@ -477,6 +505,12 @@ struct Batched {
   char *ws;
   hipStream_t st;
   int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1, W = 64, phases = 0;
+  // phase launches: 0 all on the launching stream; 1 the kinds of a phase
+  // (narrow checks, wide checks, variables) on parallel streams, joined at the
+  // end of the phase; 2 every job's phases as a chain of its own on one of up
+  // to 1 + kSideStreams parallel streams, joined once at the end
+  int streams = 0;
+  SideStreams *side = nullptr;
   BatchLayout L;
   std::vector<BatchJob> table;
   std::vector<const DeviceCode *> dev;
@@ -661,7 +695,41 @@ struct Batched {
     const BatchJob *tab = reinterpret_cast<const BatchJob *>(ws + L.off_table);
     hipLaunchKernelGGL(k_control_init, dim3(1), dim3(kBlock), 0, st, reinterpret_cast<uint32_t *>(ctl));
     if (phases) {
-      for (int ph = 0; ph < n_phases; ++ph) {
+      // streams 0..k-1: the launching stream and k - 1 side streams
+      auto stream_of = [&](int i) { return i == 0 ? st : side->s[i - 1]; };
+      auto fork = [&](int k) {
+        if (k < 2) return;
+        (void)hipEventRecord(side->fork, st);
+        for (int i = 1; i < k; ++i) (void)hipStreamWaitEvent(side->s[i - 1], side->fork, 0);
+      };
+      auto join = [&](int k) {
+        for (int i = 1; i < k; ++i) {
+          (void)hipEventRecord(side->join[i - 1], side->s[i - 1]);
+          (void)hipStreamWaitEvent(st, side->join[i - 1], 0);
+        }
+      };
+      const int n_chains = std::min(n, kSideStreams + 1);
+      if (streams == 2) fork(n_chains);
+      for (int ph = 0; ph < n_phases && streams == 2; ++ph) {
+        int phv = ph, one = 1;
+        for (int j = 0; j < n; ++j) {
+          const BatchJob &b = table[j];
+          const int s = ph - b.offset;
+          if (s < 0 || s >= 2 * b.max_iter) continue;
+          const BatchJob *tj = tab + j;  // a table of one job: the kernel sees job j alone
+          void *args[] = {(void *)&tj, (void *)&one, (void *)&phv};
+          const hipStream_t hs = stream_of(j % n_chains);
+          const int64_t cnt[4] = {0, (int64_t)b.cn_tiles_k[0] * b.G, (int64_t)b.vn_blocks * b.G,
+                                  (int64_t)b.cn_tiles_k[1] * b.G};
+          for (int kind : {1, 3, 2}) {
+            if ((kind == 2) != ((s & 1) == 1) || cnt[kind] == 0) continue;
+            ScopedTimer t(hs, "k_phase");
+            (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)cnt[kind]), dim3(kBlock), args, 0, hs);
+          }
+        }
+      }
+      if (streams == 2) join(n_chains);
+      for (int ph = 0; ph < n_phases && streams != 2; ++ph) {
         // tiles of the phase: [0] all, [1] narrow checks, [2] variables, [3] wide checks
         int64_t tiles[4] = {0, 0, 0, 0};
         for (int j = 0; j < n; ++j) {
@@ -679,12 +747,19 @@ struct Batched {
         if (tiles[0] == 0) continue;
         int phv = ph;
         void *args[] = {(void *)&tab, (void *)&n, (void *)&phv};
-        const bool mixed = tiles[2] > 0 && tiles[1] + tiles[3] > 0;
+        const bool mixed = streams == 0 && tiles[2] > 0 && tiles[1] + tiles[3] > 0;
+        int n_kinds = 0;
+        for (int kind : {1, 3, 2}) n_kinds += tiles[kind] > 0;
+        const int k_streams = streams == 1 ? n_kinds : 1;
+        fork(k_streams);
+        int i = 0;
         for (int kind : {0, 1, 3, 2}) {
           if (mixed ? kind != 0 : (kind == 0 || tiles[kind] == 0)) continue;
-          ScopedTimer t(st, "k_phase");
-          (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)tiles[kind]), dim3(kBlock), args, 0, st);
+          const hipStream_t hs = stream_of(k_streams > 1 ? i++ : 0);
+          ScopedTimer t(hs, "k_phase");
+          (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)tiles[kind]), dim3(kBlock), args, 0, hs);
         }
+        join(k_streams);
       }
     } else {
       ScopedTimer t(st, "k_persistent");
@@ -750,6 +825,7 @@ struct Batched {
     append_bytes(k, ipw);
     append_bytes(k, phases);
     append_bytes(k, stagger);  // the phase schedule bakes each phase's tile count into the graph
+    append_bytes(k, streams);
     append_bytes(k, W);
     append_bytes(k, gen);
     append_bytes(k, grid);
@@ -764,6 +840,10 @@ struct Batched {
   int run() {
     int rc = prepare();
     if (rc) return rc;
+    if (phases && streams) {
+      rc = side_streams(&side);
+      if (rc) return rc;
+    }
     // the job table is stream-ordered before the graph (or the plain launches)
     HIP_TRY(hipMemcpyAsync(ws + L.off_table, table.data(), sizeof(BatchJob) * table.size(), hipMemcpyHostToDevice,
                            st));
@@ -861,10 +941,14 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
     if (s) b.ipw = s;
     if (tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > 64) return fail(MET_EINVAL, "bad blocks_per_cu");
     b.blocks_per_cu = tuning->blocks_per_cu;
-    if (tuning->batch_flags & ~7u) return fail(MET_EINVAL, "unknown batch_flags");
-    b.stagger = !(tuning->batch_flags & MET_BATCH_NO_STAGGER);
-    b.use_graph = !(tuning->batch_flags & MET_BATCH_NO_GRAPH);
-    b.phases = (tuning->batch_flags & MET_BATCH_PHASE_LAUNCHES) ? 1 : 0;
+    const uint32_t bf = tuning->batch_flags;
+    if (bf & ~31u) return fail(MET_EINVAL, "unknown batch_flags");
+    if ((bf & MET_BATCH_KIND_STREAMS) && (bf & MET_BATCH_JOB_STREAMS))
+      return fail(MET_EINVAL, "MET_BATCH_KIND_STREAMS and MET_BATCH_JOB_STREAMS exclude each other");
+    b.stagger = !(bf & MET_BATCH_NO_STAGGER);
+    b.use_graph = !(bf & MET_BATCH_NO_GRAPH);
+    b.streams = (bf & MET_BATCH_KIND_STREAMS) ? 1 : (bf & MET_BATCH_JOB_STREAMS) ? 2 : 0;
+    b.phases = (bf & MET_BATCH_PHASE_LAUNCHES) || b.streams ? 1 : 0;
     const int w = tuning->interleave;
     if (w != 0 && w != 16 && w != 32 && w != 64) return fail(MET_EINVAL, "interleave must be 0, 16, 32 or 64");
     if (w) b.W = w;
@@ -999,15 +1083,16 @@ extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *w
       cur_ms = ms;
     }
   }
-  // one launch per phase: interleave width x steps per wave x stagger
+  // one launch per phase: interleave width x steps per wave x stagger x streams
   for (int w : met::kBatchWidths)
     for (int ipw : {4, 2, 1})
-      for (uint32_t stag : {0u, (uint32_t)MET_BATCH_NO_STAGGER}) {
+      for (uint32_t stag : {0u, (uint32_t)MET_BATCH_NO_STAGGER})
+        for (uint32_t par : {0u, (uint32_t)MET_BATCH_KIND_STREAMS, (uint32_t)MET_BATCH_JOB_STREAMS}) {
         if (w != 64 && ipw != 1) continue;
         met_tuning t{};
         t.interleave = w;
         t.check_steps_per_wave = ipw;
-        t.batch_flags = MET_BATCH_PHASE_LAUNCHES | stag;
+        t.batch_flags = MET_BATCH_PHASE_LAUNCHES | stag | par;
         float ms = 0.0f;
         rc = met::time_shape(probe, ws, st, t, 2, &ms);
         if (rc) return rc;

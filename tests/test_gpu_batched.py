@@ -63,7 +63,11 @@ def _same(a, b, tag):
                                     dict(phase_launches=True, check_steps_per_wave=2),
                                     dict(phase_launches=True, check_steps_per_wave=1, graph=False),
                                     dict(phase_launches=True, interleave=32),
-                                    dict(phase_launches=True, interleave=16, stagger=False)])
+                                    dict(phase_launches=True, interleave=16, stagger=False),
+                                    dict(streams="kinds"), dict(streams="kinds", stagger=False),
+                                    dict(streams="kinds", graph=False, interleave=32),
+                                    dict(streams="jobs"), dict(streams="jobs", stagger=False, check_steps_per_wave=2),
+                                    dict(streams="jobs", graph=False), dict(streams="jobs", interleave=16)])
 def test_batched_equals_plain_decode(mix, tuning):
     jobs = [j for j, _ in mix]
     print("batched", tuning, flush=True)
