@@ -106,11 +106,19 @@ def test_q8_first_iteration_and_determinism(prof, n, b, snr):
         np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
 
 
-def test_q8_decodes_clean_frames():
+@pytest.mark.parametrize("snr", [0.3, 0.4])
+def test_q8_decodes_clean_frames(snr):
+    """Above the waterfall the 8-bit storage decodes every frame that float
+    storage decodes, to the sent word (at SNR 0.3 one of these 40 frames is
+    stuck for both)."""
     code = met.Code.build(PROFILES["r0.1"], 16384, 8)
-    bits, llr = make_frames(16384, 40, 0.3, 13)
+    bits, llr = make_frames(16384, 40, snr, 13)
     syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
-    out = met.decode(code, torch.from_numpy(llr).to(DEV), syn, 60, c2v_q8=True)
+    d_llr = torch.from_numpy(llr).to(DEV)
+    ref = met.decode(code, d_llr, syn, 60)
+    out = met.decode(code, d_llr, syn, 60, c2v_q8=True)
     torch.cuda.synchronize()
-    assert out.converged.cpu().numpy().all()
-    np.testing.assert_array_equal(out.bits.cpu().numpy(), bits)
+    ok = ref.converged.cpu().numpy() == 1
+    assert ok.sum() >= 39
+    assert np.all(out.converged.cpu().numpy()[ok] == 1)
+    np.testing.assert_array_equal(out.bits.cpu().numpy()[ok], bits[ok])
