@@ -27,7 +27,10 @@
 // unit completes 2.3 times the check tiles of the youngest), while short
 // ordinary blocks rotate it.  The persistent launch wins where phases are
 // short and frames converge: it stops at the first barrier after every frame
-// has stopped, while a graph of launches runs to the end.
+// has stopped, while a graph of launches runs to the end.  The launches of a
+// phase can also run on parallel streams (by kind of tile, or each job's
+// launches as a chain of its own); where every launch fills the GPU that only
+// splits the same memory path between them.
 #include "met_gpu.h"
 
 namespace met {
