@@ -373,7 +373,9 @@ def run_mix(args, cpu) -> dict:
     p_ms = timed_plain(plain, args.steps)
     del wss
     dec = met.BatchedDecoder(check_steps_per_wave=args.check_steps, blocks_per_cu=args.blocks_per_cu,
-                             phase_launches=args.schedule == "phase", stagger=not args.no_stagger)
+                             phase_launches=args.schedule in ("phase", "kinds", "jobs", "serial"),
+                             stagger=not args.no_stagger,
+                             streams=args.schedule if args.schedule in ("kinds", "jobs", "serial") else "one")
     shape = None
     if args.schedule == "auto" and not args.no_autotune and not args.check_steps and not args.blocks_per_cu:
         shape = dec.autotune(jobs)  # outside the timed region
@@ -412,8 +414,15 @@ def run_mix(args, cpu) -> dict:
         d["plain_fer"] = fer_summary(p_out[len(per_job)], bits)["fer"]
         per_job.append(d)
     step_bytes = sum(check_bytes.values()) + var_bytes
-    kl, kms = b_kt.get(bk, (0, 0.0))
+    # the phase launches are timed per kind of tile (k_phase:...): pooled here
+    kl = sum(v[0] for k, v in b_kt.items() if k.split(":")[0] == bk)
+    kms = sum(v[1] for k, v in b_kt.items() if k.split(":")[0] == bk)
     roof = roofline(bk, step_bytes * args.steps, kl, kms, measured_traffic(bk, wl))
+    # the whole step's algorithmic bytes over the graph replay's step time:
+    # the rate of the schedule as a whole (with launches on parallel streams
+    # the per-launch durations above overlap)
+    roof["step_achieved"] = round(step_bytes / (g_ms / args.steps * 1e-3) / 1e9, 1)
+    roof["step_frac"] = round(roof["step_achieved"] / HBM_PEAK_GBS, 4)
     # the same launches priced by the 16-byte-per-edge model (both message
     # arrays stored), for comparison; `frac` above uses the posterior form the
     # kernels implement (c2v stored, v2c re-formed from the posteriors)
@@ -440,6 +449,8 @@ def run_mix(args, cpu) -> dict:
             "N": n, "frames_per_job": B, "profiles": list(MIX), "code_seeds": [CODE_SEED[p] for p in MIX],
             "frame_seed": FRAME_SEED, "mode": "batched", "schedule": sched,
             "stagger": not (dec.tuning.batch_flags & 1),
+            "streams": ("kinds" if dec.tuning.batch_flags & 8 else "jobs" if dec.tuning.batch_flags & 16
+                        else "serial" if dec.tuning.batch_flags & 32 else "one"),
             "interleave": int((shape or {}).get("interleave") or 64),
         },
         "roofline": roof,
@@ -864,9 +875,11 @@ def main() -> int:
     ap.add_argument("--vn-chunk", type=int, default=0, help="variable-kernel gathers in flight (0 = default)")
     ap.add_argument("--blocks-per-cu", type=int, default=0, help="persistent blocks per CU (0 = default)")
     ap.add_argument("--no-autotune", action="store_true", help="mix: keep the default persistent launch shape")
-    ap.add_argument("--schedule", default="auto", choices=("auto", "phase", "persistent"),
-                    help="mix: batched schedule (auto = autotuned; phase = one launch per phase, persistent = one "
-                         "persistent launch, both with the default shape)")
+    ap.add_argument("--schedule", default="auto", choices=("auto", "phase", "kinds", "jobs", "serial", "persistent"),
+                    help="mix: batched schedule (auto = autotuned; phase = one launch per phase, kinds = the same "
+                         "with the launches of a phase on parallel streams, jobs = each job's launches a chain on "
+                         "parallel streams, serial = those chains one job after the other, persistent = one persistent launch; all "
+                         "with the default shape)")
     ap.add_argument("--no-stagger", action="store_true", help="mix: all jobs start in the same phase")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=50, help="iterations per frame in the CPU sample")

@@ -354,6 +354,11 @@ int met_wbp_backward(const met_code *c, const float *grad_posterior, int32_t B, 
                                    device (default priority) and keeps; calls
                                    that use them must not overlap on one
                                    device */
+#define MET_BATCH_JOBS_IN_TURN 32u /* batched, implies MET_BATCH_PHASE_LAUNCHES:
+                                   the same per-job chains one job after the
+                                   other on the launching stream (each job's
+                                   data stays in the caches between its
+                                   launches); excludes the two above */
 
 typedef struct {
   int32_t check_steps_per_wave; /* 1, 2 or 4: steps of 64/W checks each wave of

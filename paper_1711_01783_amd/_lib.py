@@ -69,6 +69,7 @@ MET_BATCH_NO_GRAPH = 2
 MET_BATCH_PHASE_LAUNCHES = 4
 MET_BATCH_KIND_STREAMS = 8
 MET_BATCH_JOB_STREAMS = 16
+MET_BATCH_JOBS_IN_TURN = 32
 
 
 class met_tuning(ctypes.Structure):

@@ -6,7 +6,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from ._lib import (MET_BATCH_JOB_STREAMS, MET_BATCH_KIND_STREAMS, MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER,
+from ._lib import (MET_BATCH_JOB_STREAMS, MET_BATCH_JOBS_IN_TURN, MET_BATCH_KIND_STREAMS, MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER,
                    MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_C2V_Q8, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
                    met_check_class,
                    met_code_stats, met_job, met_kernel_time, met_profile, met_tuning)
@@ -319,10 +319,12 @@ class BatchedDecoder:
     stagger / graph / interleave (frames per group: 16, 32 or 64) /
     phase_launches / streams select launch shapes; results do not depend on
     them.  streams (phase launches only): "one" (default), "kinds" (the
-    launches of a phase on parallel streams) or "jobs" (each job's launches a
-    chain of their own on parallel streams)."""
+    launches of a phase on parallel streams), "jobs" (each job's launches a
+    chain of their own on parallel streams) or "serial" (those chains one job
+    after the other)."""
 
-    _STREAMS = {"one": 0, "kinds": MET_BATCH_KIND_STREAMS, "jobs": MET_BATCH_JOB_STREAMS}
+    _STREAMS = {"one": 0, "kinds": MET_BATCH_KIND_STREAMS, "jobs": MET_BATCH_JOB_STREAMS,
+                "serial": MET_BATCH_JOBS_IN_TURN}
 
     def __init__(self, check_steps_per_wave: int = 0, blocks_per_cu: int = 0, stagger: bool = True,
                  graph: bool = True, interleave: int = 0, phase_launches: bool = False, streams: str = "one"):
@@ -388,11 +390,13 @@ class BatchedDecoder:
                                        ctypes.byref(best), ctypes.byref(ms), _stream_ptr(stream)))
         graph = not (self.tuning.batch_flags & MET_BATCH_NO_GRAPH)
         self.tuning = best
-        keep = MET_BATCH_NO_STAGGER | MET_BATCH_PHASE_LAUNCHES | MET_BATCH_KIND_STREAMS | MET_BATCH_JOB_STREAMS
+        keep = (MET_BATCH_NO_STAGGER | MET_BATCH_PHASE_LAUNCHES | MET_BATCH_KIND_STREAMS | MET_BATCH_JOB_STREAMS
+                | MET_BATCH_JOBS_IN_TURN)
         self.tuning.batch_flags = (best.batch_flags & keep) | (0 if graph else MET_BATCH_NO_GRAPH)
         return {"schedule": "phase launches" if best.batch_flags & MET_BATCH_PHASE_LAUNCHES else "persistent",
                 "streams": ("kinds" if best.batch_flags & MET_BATCH_KIND_STREAMS else
-                            "jobs" if best.batch_flags & MET_BATCH_JOB_STREAMS else "one"),
+                            "jobs" if best.batch_flags & MET_BATCH_JOB_STREAMS else
+                            "serial" if best.batch_flags & MET_BATCH_JOBS_IN_TURN else "one"),
                 "check_steps_per_wave": int(best.check_steps_per_wave), "blocks_per_cu": int(best.blocks_per_cu),
                 "interleave": int(best.interleave),
                 "stagger": not (best.batch_flags & MET_BATCH_NO_STAGGER), "probe_ms": float(ms.value)}

@@ -502,6 +502,16 @@ void append_bytes(std::vector<uint8_t> &k, const T &v) {
   k.insert(k.end(), p, p + sizeof(T));
 }
 
+// Per-launch timer names of the phase launches, by kind of tile.
+const char *phase_timer_name(int kind) {
+  switch (kind) {
+    case 1: return "k_phase:checks(3,1)(2,1)";
+    case 2: return "k_phase:variables";
+    case 3: return "k_phase:checks(other)";
+    default: return "k_phase:mixed";
+  }
+}
+
 struct Batched {
   const met_job *jobs;
   int n;
@@ -511,7 +521,8 @@ struct Batched {
   // phase launches: 0 all on the launching stream; 1 the kinds of a phase
   // (narrow checks, wide checks, variables) on parallel streams, joined at the
   // end of the phase; 2 every job's phases as a chain of its own on one of up
-  // to 1 + kSideStreams parallel streams, joined once at the end
+  // to 1 + kSideStreams parallel streams, joined once at the end; 3 the same
+  // chains one job after the other on the launching stream
   int streams = 0;
   SideStreams *side = nullptr;
   BatchLayout L;
@@ -711,28 +722,29 @@ struct Batched {
           (void)hipStreamWaitEvent(st, side->join[i - 1], 0);
         }
       };
-      const int n_chains = std::min(n, kSideStreams + 1);
-      if (streams == 2) fork(n_chains);
-      for (int ph = 0; ph < n_phases && streams == 2; ++ph) {
-        int phv = ph, one = 1;
-        for (int j = 0; j < n; ++j) {
-          const BatchJob &b = table[j];
-          const int s = ph - b.offset;
-          if (s < 0 || s >= 2 * b.max_iter) continue;
-          const BatchJob *tj = tab + j;  // a table of one job: the kernel sees job j alone
+      // per-job chains (streams 2: on up to 1 + kSideStreams parallel streams;
+      // streams 3: one job after the other on the launching stream)
+      const bool chains = streams >= 2;
+      const int n_chains = streams == 2 ? std::min(n, kSideStreams + 1) : 1;
+      if (chains) fork(n_chains);
+      for (int j = 0; j < n && chains; ++j) {
+        const BatchJob &b = table[j];
+        const BatchJob *tj = tab + j;  // a table of one job: the kernel sees job j alone
+        const hipStream_t hs = stream_of(j % n_chains);
+        const int64_t cnt[4] = {0, (int64_t)b.cn_tiles_k[0] * b.G, (int64_t)b.vn_blocks * b.G,
+                                (int64_t)b.cn_tiles_k[1] * b.G};
+        for (int ph = b.offset; ph < b.offset + 2 * b.max_iter; ++ph) {
+          int phv = ph, one = 1;
           void *args[] = {(void *)&tj, (void *)&one, (void *)&phv};
-          const hipStream_t hs = stream_of(j % n_chains);
-          const int64_t cnt[4] = {0, (int64_t)b.cn_tiles_k[0] * b.G, (int64_t)b.vn_blocks * b.G,
-                                  (int64_t)b.cn_tiles_k[1] * b.G};
           for (int kind : {1, 3, 2}) {
-            if ((kind == 2) != ((s & 1) == 1) || cnt[kind] == 0) continue;
-            ScopedTimer t(hs, "k_phase");
+            if ((kind == 2) != (((ph - b.offset) & 1) == 1) || cnt[kind] == 0) continue;
+            ScopedTimer t(hs, phase_timer_name(kind));
             (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)cnt[kind]), dim3(kBlock), args, 0, hs);
           }
         }
       }
-      if (streams == 2) join(n_chains);
-      for (int ph = 0; ph < n_phases && streams != 2; ++ph) {
+      if (chains) join(n_chains);
+      for (int ph = 0; ph < n_phases && !chains; ++ph) {
         // tiles of the phase: [0] all, [1] narrow checks, [2] variables, [3] wide checks
         int64_t tiles[4] = {0, 0, 0, 0};
         for (int j = 0; j < n; ++j) {
@@ -759,7 +771,7 @@ struct Batched {
         for (int kind : {0, 1, 3, 2}) {
           if (mixed ? kind != 0 : (kind == 0 || tiles[kind] == 0)) continue;
           const hipStream_t hs = stream_of(k_streams > 1 ? i++ : 0);
-          ScopedTimer t(hs, "k_phase");
+          ScopedTimer t(hs, phase_timer_name(kind));
           (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)tiles[kind]), dim3(kBlock), args, 0, hs);
         }
         join(k_streams);
@@ -945,12 +957,13 @@ extern "C" int met_decode_batched(const met_job *jobs, int32_t n_jobs, void *wor
     if (tuning->blocks_per_cu < 0 || tuning->blocks_per_cu > 64) return fail(MET_EINVAL, "bad blocks_per_cu");
     b.blocks_per_cu = tuning->blocks_per_cu;
     const uint32_t bf = tuning->batch_flags;
-    if (bf & ~31u) return fail(MET_EINVAL, "unknown batch_flags");
-    if ((bf & MET_BATCH_KIND_STREAMS) && (bf & MET_BATCH_JOB_STREAMS))
-      return fail(MET_EINVAL, "MET_BATCH_KIND_STREAMS and MET_BATCH_JOB_STREAMS exclude each other");
+    if (bf & ~63u) return fail(MET_EINVAL, "unknown batch_flags");
+    const uint32_t order = bf & (MET_BATCH_KIND_STREAMS | MET_BATCH_JOB_STREAMS | MET_BATCH_JOBS_IN_TURN);
+    if (order & (order - 1))
+      return fail(MET_EINVAL, "MET_BATCH_KIND_STREAMS, MET_BATCH_JOB_STREAMS and MET_BATCH_JOBS_IN_TURN exclude each other");
     b.stagger = !(bf & MET_BATCH_NO_STAGGER);
     b.use_graph = !(bf & MET_BATCH_NO_GRAPH);
-    b.streams = (bf & MET_BATCH_KIND_STREAMS) ? 1 : (bf & MET_BATCH_JOB_STREAMS) ? 2 : 0;
+    b.streams = (bf & MET_BATCH_KIND_STREAMS) ? 1 : (bf & MET_BATCH_JOB_STREAMS) ? 2 : (bf & MET_BATCH_JOBS_IN_TURN) ? 3 : 0;
     b.phases = (bf & MET_BATCH_PHASE_LAUNCHES) || b.streams ? 1 : 0;
     const int w = tuning->interleave;
     if (w != 0 && w != 16 && w != 32 && w != 64) return fail(MET_EINVAL, "interleave must be 0, 16, 32 or 64");
@@ -1090,7 +1103,8 @@ extern "C" int met_batched_autotune(const met_job *jobs, int32_t n_jobs, void *w
   for (int w : met::kBatchWidths)
     for (int ipw : {4, 2, 1})
       for (uint32_t stag : {0u, (uint32_t)MET_BATCH_NO_STAGGER})
-        for (uint32_t par : {0u, (uint32_t)MET_BATCH_KIND_STREAMS, (uint32_t)MET_BATCH_JOB_STREAMS}) {
+        for (uint32_t par : {0u, (uint32_t)MET_BATCH_KIND_STREAMS, (uint32_t)MET_BATCH_JOB_STREAMS,
+                             (uint32_t)MET_BATCH_JOBS_IN_TURN}) {
         if (w != 64 && ipw != 1) continue;
         met_tuning t{};
         t.interleave = w;

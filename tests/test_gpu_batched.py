@@ -67,7 +67,8 @@ def _same(a, b, tag):
                                     dict(streams="kinds"), dict(streams="kinds", stagger=False),
                                     dict(streams="kinds", graph=False, interleave=32),
                                     dict(streams="jobs"), dict(streams="jobs", stagger=False, check_steps_per_wave=2),
-                                    dict(streams="jobs", graph=False), dict(streams="jobs", interleave=16)])
+                                    dict(streams="jobs", graph=False), dict(streams="jobs", interleave=16),
+                                    dict(streams="serial"), dict(streams="serial", graph=False, stagger=False)])
 def test_batched_equals_plain_decode(mix, tuning):
     jobs = [j for j, _ in mix]
     print("batched", tuning, flush=True)

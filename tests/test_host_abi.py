@@ -225,12 +225,15 @@ def test_batched_argument_validation_without_gpu():
     t.check_steps_per_wave = 3
     assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
     t.check_steps_per_wave = 0
-    t.batch_flags = 32   # first unknown flag
+    t.batch_flags = 64   # first unknown flag
     assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
     assert "batch_flags" in L.met_last_error().decode()
-    t.batch_flags = _lib.MET_BATCH_KIND_STREAMS | _lib.MET_BATCH_JOB_STREAMS
-    assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
-    assert "exclude" in L.met_last_error().decode()
+    for f in ((_lib.MET_BATCH_KIND_STREAMS | _lib.MET_BATCH_JOB_STREAMS),
+              (_lib.MET_BATCH_JOB_STREAMS | _lib.MET_BATCH_JOBS_IN_TURN),
+              (_lib.MET_BATCH_KIND_STREAMS | _lib.MET_BATCH_JOBS_IN_TURN)):
+        t.batch_flags = f
+        assert L.met_decode_batched(jobs, 2, P(256), both, ctypes.byref(t), None) == -1
+        assert "exclude" in L.met_last_error().decode()
     assert L.met_batched_check(None, None) == -1
 
 
