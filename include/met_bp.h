@@ -392,7 +392,9 @@ int met_decode_ex(const met_code *c, const float *llr, const uint8_t *syn, int32
  * of 64 frames).  The launch is persistent: its grid is sized to be resident
  * at once and steps through the iterations of all jobs with a grid-wide
  * barrier between phases.  Batches holding codes with check degrees that have
- * no compiled shape run with one check step per wave. */
+ * no compiled shape run their check tiles with one step per wave, except the
+ * (3,1) / (2,1) checks where the schedule gives them launches of their own
+ * (phase launches without stagger, or on parallel streams). */
 typedef struct {
   const met_code *code;
   const float *llr;     /* dev f32 [B][N] */

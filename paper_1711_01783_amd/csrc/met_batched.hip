@@ -518,6 +518,7 @@ struct Batched {
   char *ws;
   hipStream_t st;
   int ipw = 4, blocks_per_cu = 0, stagger = 1, use_graph = 1, W = 64, phases = 0;
+  int ipw_narrow = 4;  // steps per wave of the (3,1) / (2,1) check tiles
   // phase launches: 0 all on the launching stream; 1 the kinds of a phase
   // (narrow checks, wide checks, variables) on parallel streams, joined at the
   // end of the phase; 2 every job's phases as a chain of its own on one of up
@@ -534,11 +535,20 @@ struct Batched {
 
   template <int KIND>
   const void *phase_kernel_k() const {
-    if (W == 32) return gen ? (const void *)k_phase<1, true, 32, KIND> : (const void *)k_phase<1, false, 32, KIND>;
-    if (W == 16) return gen ? (const void *)k_phase<1, true, 16, KIND> : (const void *)k_phase<1, false, 16, KIND>;
-    if (gen) return (const void *)k_phase<1, true, 64, KIND>;
-    return ipw == 4 ? (const void *)k_phase<4, false, 64, KIND>
-                    : ipw == 2 ? (const void *)k_phase<2, false, 64, KIND> : (const void *)k_phase<1, false, 64, KIND>;
+    // the narrow-check and variable launches hold no run-time-degree body
+    if constexpr (KIND == 1 || KIND == 2) {
+      if (W == 32) return (const void *)k_phase<1, false, 32, KIND>;
+      if (W == 16) return (const void *)k_phase<1, false, 16, KIND>;
+      const int s = KIND == 1 ? ipw_narrow : 1;  // variable tiles have no steps
+      return s == 4 ? (const void *)k_phase<4, false, 64, KIND>
+                    : s == 2 ? (const void *)k_phase<2, false, 64, KIND> : (const void *)k_phase<1, false, 64, KIND>;
+    } else {
+      if (W == 32) return gen ? (const void *)k_phase<1, true, 32, KIND> : (const void *)k_phase<1, false, 32, KIND>;
+      if (W == 16) return gen ? (const void *)k_phase<1, true, 16, KIND> : (const void *)k_phase<1, false, 16, KIND>;
+      if (gen) return (const void *)k_phase<1, true, 64, KIND>;
+      return ipw == 4 ? (const void *)k_phase<4, false, 64, KIND>
+                      : ipw == 2 ? (const void *)k_phase<2, false, 64, KIND> : (const void *)k_phase<1, false, 64, KIND>;
+    }
   }
   const void *phase_kernel(int kind) const {
     switch (kind) {
@@ -622,19 +632,29 @@ struct Batched {
         if (cls[k].shape == kShapeGeneric) gen = true;
       }
     }
-    if (gen) ipw = 1;
+    // Run-time-degree classes: check tiles take one step per wave in every
+    // launch that holds their body (the persistent launch, the wide-check
+    // launches, a phase launch that holds every body); the (3,1) / (2,1)
+    // checks keep the requested steps where they have launches of their own.
+    ipw_narrow = ipw;
+    if (gen) {
+      ipw = 1;
+      const bool own_narrow = phases && (streams != 0 || !stagger);
+      if (!own_narrow) ipw_narrow = 1;
+    }
     for (int j = 0; j < n; ++j) {
       BatchJob &b = table[j];
       b.cn_tiles = 0;
       b.cn_tiles_k[0] = b.cn_tiles_k[1] = 0;
       for (int k = 0; k < b.n_classes; ++k) {
         const ClassArgs &ck = b.cls[k];
-        const int ip = shape_ipw(ck.shape, ipw);
+        const int wide = (ck.shape == 0 || ck.shape == 1) ? 0 : 1;
+        const int ip = shape_ipw(ck.shape, wide ? ipw : ipw_narrow);
         const int64_t per = (int64_t)kWavesPerBlock * ip * (64 / W);  // checks per tile
         b.cls_blocks[k] = (int32_t)((ck.n_checks + per - 1) / per);
         b.cn_tiles += b.cls_blocks[k];
-        b.cls_wide[k] = (ck.shape == 0 || ck.shape == 1) ? 0 : 1;
-        b.cn_tiles_k[b.cls_wide[k]] += b.cls_blocks[k];
+        b.cls_wide[k] = wide;
+        b.cn_tiles_k[wide] += b.cls_blocks[k];
       }
     }
     n_phases = max_end;
@@ -838,6 +858,7 @@ struct Batched {
     (void)hipGetDevice(&dev);
     append_bytes(k, dev);
     append_bytes(k, ipw);
+    append_bytes(k, ipw_narrow);
     append_bytes(k, phases);
     append_bytes(k, stagger);  // the phase schedule bakes each phase's tile count into the graph
     append_bytes(k, streams);

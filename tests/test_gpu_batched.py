@@ -145,6 +145,15 @@ def test_tree_codes_with_runtime_degree_checks():
         out = met.decode_batched(jobs, interleave=w)
         torch.cuda.synchronize()
         _same(out, ref, "trees, interleave %d" % w)
+    # schedules where the (3,1) / (2,1) checks have launches of their own keep
+    # several steps per wave next to the run-time-degree classes
+    for kw in (dict(phase_launches=True, stagger=False), dict(phase_launches=True, stagger=False,
+                                                             check_steps_per_wave=2),
+               dict(phase_launches=True), dict(streams="kinds"), dict(streams="serial", graph=False),
+               dict(streams="jobs", stagger=False)):
+        out = met.decode_batched(jobs, **kw)
+        torch.cuda.synchronize()
+        _same(out, ref, "trees, %s" % kw)
 
 
 def test_autotuner_picks_a_valid_shape_and_caches_it(mix):
