@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
 // (the bulk of the work, as lean as the plain decoder's check kernel), KIND 3
 // the check tiles of every other shape, KIND 2 the variable tiles.
 template <int IPW, bool GEN, int W, int KIND>
-__global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_jobs, int phase) {
+__device__ __forceinline__ void phase_body(const BatchJob *table, int n_jobs, int phase) {
   CJob *jobs = (CJob *)table;
   int64_t t = blockIdx.x;
   for (int j = 0; j < n_jobs; ++j) {
@@ -403,6 +403,21 @@ __global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_j
     }
     t -= cnt;
   }
+}
+
+template <int IPW, bool GEN, int W, int KIND>
+__global__ __launch_bounds__(kBlock) void k_phase(const BatchJob *table, int n_jobs, int phase) {
+  phase_body<IPW, GEN, W, KIND>(table, n_jobs, phase);
+}
+
+// The (3,1) / (2,1) check launches and the variable launches, compiled for
+// eight resident waves per SIMD: the job table's parameters otherwise take
+// more than a hundred scalar registers, which leaves room for seven.
+template <int IPW, int W, int KIND>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_phase_lean(
+    const BatchJob *table, int n_jobs, int phase) {
+  static_assert(KIND == 1 || KIND == 2, "lean launches hold no run-time-degree body");
+  phase_body<IPW, false, W, KIND>(table, n_jobs, phase);
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_floats(float *x, int64_t n) {
@@ -537,11 +552,11 @@ struct Batched {
   const void *phase_kernel_k() const {
     // the narrow-check and variable launches hold no run-time-degree body
     if constexpr (KIND == 1 || KIND == 2) {
-      if (W == 32) return (const void *)k_phase<1, false, 32, KIND>;
-      if (W == 16) return (const void *)k_phase<1, false, 16, KIND>;
+      if (W == 32) return (const void *)k_phase_lean<1, 32, KIND>;
+      if (W == 16) return (const void *)k_phase_lean<1, 16, KIND>;
       const int s = KIND == 1 ? ipw_narrow : 1;  // variable tiles have no steps
-      return s == 4 ? (const void *)k_phase<4, false, 64, KIND>
-                    : s == 2 ? (const void *)k_phase<2, false, 64, KIND> : (const void *)k_phase<1, false, 64, KIND>;
+      return s == 4 ? (const void *)k_phase_lean<4, 64, KIND>
+                    : s == 2 ? (const void *)k_phase_lean<2, 64, KIND> : (const void *)k_phase_lean<1, 64, KIND>;
     } else {
       if (W == 32) return gen ? (const void *)k_phase<1, true, 32, KIND> : (const void *)k_phase<1, false, 32, KIND>;
       if (W == 16) return gen ? (const void *)k_phase<1, true, 16, KIND> : (const void *)k_phase<1, false, 16, KIND>;
