@@ -161,11 +161,27 @@ using CJob = const BatchJob;  // the host pass only parses device code
 // PERSIST: inside the persistent launch (words written by earlier phases of the
 // same launch are read with vector loads); false in the phase launches, where
 // every earlier phase is an earlier launch and such words are constant.
+// Frame group and tile within it of tile t of a job's phase, n tiles per
+// group: in 32 bits when the phase has fewer than 2^32 tiles (always, at the
+// sizes a workspace can hold), with no division for the first group (a 64-bit
+// division is a long sequence of scalar instructions per wave).
+__device__ __forceinline__ void split_tile(int64_t t, int32_t n, int G, int64_t *g, int64_t *r) {
+  if ((int64_t)n * G <= (int64_t)UINT32_MAX) {
+    const uint32_t u = (uint32_t)t, m = (uint32_t)n;
+    const uint32_t q = u < m ? 0u : u / m;
+    *g = q;
+    *r = u - q * m;
+  } else {
+    *g = t / n;
+    *r = t % n;
+  }
+}
+
 template <int IPW, bool GEN, int W, int KF = -1, bool PERSIST = true>
 __device__ __forceinline__ void check_tile(CJob *jobs, int j, int l, int64_t t) {
   const int32_t cn_tiles = KF < 0 ? jobs[j].cn_tiles : jobs[j].cn_tiles_k[KF < 0 ? 0 : KF];
-  const int64_t g = t / cn_tiles;
-  int64_t r = t % cn_tiles;
+  int64_t g = 0, r = 0;
+  split_tile(t, cn_tiles, jobs[j].G, &g, &r);
   int c = 0;
   if constexpr (KF < 0) {
     while (r >= jobs[j].cls_blocks[c]) r -= jobs[j].cls_blocks[c++];
@@ -212,7 +228,9 @@ __device__ __forceinline__ void variable_tile(CJob *jobs, int j, int l, int64_t 
   vp.it = l;
   vp.retire = jobs[j].early && l >= 2;
   vp.unsat = jobs[j].unsat + (size_t)((l - 1) & 1) * jobs[j].G;
-  variable_body<W, 16, PERSIST>(vp, t % vb, (int)(t / vb));
+  int64_t g = 0, r = 0;
+  split_tile(t, vb, jobs[j].G, &g, &r);
+  variable_body<W, 16, PERSIST>(vp, r, (int)g);
 }
 
 // Phase step of job j: s = phase - offset; even s: check update of iteration
@@ -517,6 +535,10 @@ void append_bytes(std::vector<uint8_t> &k, const T &v) {
   k.insert(k.end(), p, p + sizeof(T));
 }
 
+// Narrow check classes with at least this many tiles (about eight blocks per
+// compute unit) fill the GPU in a launch of their own.
+constexpr int64_t kOwnLaunchTiles = 2048;
+
 // Per-launch timer names of the phase launches, by kind of tile.
 const char *phase_timer_name(int kind) {
   switch (kind) {
@@ -773,6 +795,10 @@ struct Batched {
           void *args[] = {(void *)&tj, (void *)&one, (void *)&phv};
           for (int kind : {1, 3, 2}) {
             if ((kind == 2) != (((ph - b.offset) & 1) == 1) || cnt[kind] == 0) continue;
+            if (kind == 1 && narrow_fills(j)) {
+              launch_narrow_plain<kBatchW>(ph, j, hs);
+              continue;
+            }
             ScopedTimer t(hs, phase_timer_name(kind));
             (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)cnt[kind]), dim3(kBlock), args, 0, hs);
           }
@@ -782,11 +808,13 @@ struct Batched {
       for (int ph = 0; ph < n_phases && !chains; ++ph) {
         // tiles of the phase: [0] all, [1] narrow checks, [2] variables, [3] wide checks
         int64_t tiles[4] = {0, 0, 0, 0};
+        std::vector<int> narrow_jobs;  // jobs with (3,1) / (2,1) tiles in this phase
         for (int j = 0; j < n; ++j) {
           const BatchJob &b = table[j];
           const int s = ph - b.offset;
           if (s < 0 || s >= 2 * b.max_iter) continue;
           if ((s & 1) == 0) {
+            if (b.cn_tiles_k[0] > 0) narrow_jobs.push_back(j);
             tiles[1] += (int64_t)b.cn_tiles_k[0] * b.G;
             tiles[3] += (int64_t)b.cn_tiles_k[1] * b.G;
           } else {
@@ -806,6 +834,16 @@ struct Batched {
         for (int kind : {0, 1, 3, 2}) {
           if (mixed ? kind != 0 : (kind == 0 || tiles[kind] == 0)) continue;
           const hipStream_t hs = stream_of(k_streams > 1 ? i++ : 0);
+          if (kind == 1) {
+            // jobs whose narrow classes fill the GPU on their own take the
+            // plain decoder's launches; the others share one launch
+            bool own = true;
+            for (int j : narrow_jobs) own = own && narrow_fills(j);
+            if (own) {
+              for (int j : narrow_jobs) launch_narrow_plain<kBatchW>(ph, j, hs);
+              continue;
+            }
+          }
           ScopedTimer t(hs, phase_timer_name(kind));
           (void)hipLaunchKernel(phase_kernel(kind), dim3((unsigned)tiles[kind]), dim3(kBlock), args, 0, hs);
         }
@@ -886,6 +924,35 @@ struct Batched {
       append_bytes(k, jobs[j].code->uid);  // a new code at a freed code's address must not match
     }
     return k;
+  }
+
+  // Every (3,1) / (2,1) class of job j fills the GPU in a launch of its own.
+  bool narrow_fills(int j) const {
+    const BatchJob &b = table[j];
+    for (int c = 0; c < b.n_classes; ++c)
+      if (!b.cls_wide[c] && (int64_t)b.cls_blocks[c] * b.G < kOwnLaunchTiles) return false;
+    return true;
+  }
+
+  // The (3,1) / (2,1) checks of job j at phase ph as the plain decoder
+  // launches them: one launch per class, parameters by value.
+  template <int kBatchW>
+  void launch_narrow_plain(int ph, int j, hipStream_t hs) {
+    const BatchJob &b = table[j];
+    const int l = (ph - b.offset) / 2 + 1;
+    CheckParams p = b.cp;
+    p.it = l;
+    p.flags = b.early && l >= 2 ? F_TEST : 0;
+    p.Pin = l == 1 ? b.L2 : b.P;
+    p.B1in = b.B1 + (size_t)((l - 1) & 1) * b.leaf_words;
+    p.B1out = b.B1 + (size_t)(l & 1) * b.leaf_words;
+    p.unsat = b.unsat + (size_t)((l - 1) & 1) * b.G;
+    for (int c = 0; c < b.n_classes; ++c) {
+      if (b.cls_wide[c]) continue;
+      p.unsat_clear = c == 0 ? b.unsat + (size_t)(l & 1) * b.G : nullptr;
+      ScopedTimer t(hs, phase_timer_name(1));
+      launch_check<kBatchW, float>(p, b.cls[c], M_MAIN, ipw_narrow, b.G, hs);
+    }
   }
 
   int run() {
