@@ -83,6 +83,20 @@ def test_batched_equals_plain_decode(mix, tuning):
     assert out[0].converged.cpu().numpy().mean() > 0.3
 
 
+@pytest.mark.parametrize("tuning", [dict(phase_launches=True, stagger=False), dict(streams="kinds"),
+                                    dict(streams="jobs", stagger=False), dict(streams="serial", graph=False)])
+def test_jobs_whose_checks_fill_the_gpu(tuning):
+    """Jobs large enough that their (3,1) / (2,1) check classes take launches
+    of their own (the plain decoder's check kernels) next to a small job that
+    shares the batched launch: every output equals the plain decode's."""
+    jobs = [_job("r0.1", 65536, 64, 0.19, 24, 51)[0], _job("r0.05", 65536, 64, 0.10, 18, 52)[0],
+            _job("r0.02", 9000, 24, 0.065, 30, 53)[0]]
+    print("large jobs", tuning, flush=True)
+    out = met.BatchedDecoder(**tuning)(jobs)
+    torch.cuda.synchronize()
+    _same(out, _plain(jobs), str(tuning))
+
+
 def test_graph_replay_and_reuse_of_outputs(mix):
     jobs = [j for j, _ in mix]
     ref = _plain(jobs)
