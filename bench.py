@@ -428,10 +428,12 @@ def run_mix(args, cpu) -> dict:
         bk = narrow
         kl, kms = b_kt[narrow]
         roof_bytes = check_bytes.get("k_check<3,1>", 0.0) + check_bytes.get("k_check<2,1>", 0.0)
+        pooled = False
     else:
         kl = sum(v[0] for k, v in b_kt.items() if k.split(":")[0] == bk)
         kms = sum(v[1] for k, v in b_kt.items() if k.split(":")[0] == bk)
         roof_bytes = step_bytes
+        pooled = True
     roof = roofline(bk, roof_bytes * args.steps, kl, kms, measured_traffic(bk, wl))
     # the whole step's algorithmic bytes over the graph replay's step time:
     # the rate of the schedule as a whole (with launches on parallel streams
@@ -446,10 +448,15 @@ def run_mix(args, cpu) -> dict:
     roof["model"] = ("posterior form: c2v read and written per message edge, posteriors gathered once per "
                      "distinct row, leaf inputs, syndrome and decision bits (class_bytes_per_frame, "
                      "variable_bytes_per_frame)")
-    mat_launch = mat * args.steps / max(1, kl)
-    roof["materialised_16B_model"] = {
-        "bytes_per_launch": round(mat_launch),
-        "frac": round(mat_launch / (kms * 1e-3 / max(1, kl)) / 1e9 / HBM_PEAK_GBS, 4) if kms > 0 else None}
+    if pooled:  # launches that carry the whole step: per launch
+        mat_launch = mat * args.steps / max(1, kl)
+        roof["materialised_16B_model"] = {
+            "bytes_per_launch": round(mat_launch),
+            "frac": round(mat_launch / (kms * 1e-3 / max(1, kl)) / 1e9 / HBM_PEAK_GBS, 4) if kms > 0 else None}
+    else:  # the model prices the whole iteration: against the step time
+        roof["materialised_16B_model"] = {
+            "bytes_per_step": round(mat),
+            "step_frac": round(mat / (g_ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     pl, pms = p_kt.get("k_check<3,1>", (0, 0.0))
     plain_roof = roofline("k_check<3,1>", check_bytes.get("k_check<3,1>", 0.0) * args.steps, pl, pms,
                           measured_traffic("k_check<3,1>", wl))
