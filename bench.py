@@ -685,7 +685,7 @@ def run_wbp_train(args) -> dict:
     from paper_1711_01783_amd import wbp
 
     prof, n, B = args.profile, args.n, args.frames
-    L, k = args.iters, args.ckpt
+    L, k = args.iters, args.ckpt or 10  # the training configuration keeps every 10th state
     snr = args.snr if args.snr is not None else BJ_SNR[prof]
     batches = [_wbp_setup(prof, n, B, snr, FRAME_SEED + 1000 * r) for r in range(4)]
     code = batches[0][0]
@@ -877,7 +877,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="mix", choices=("mix", "single", "wbp-train", "wbp-eval", "deg1", "mdr"))
     ap.add_argument("--iters", type=int, default=50, help="weighted BP: unrolled iterations")
-    ap.add_argument("--ckpt", type=int, default=0, help="weighted BP: checkpoint interval (0 = about sqrt)")
+    ap.add_argument("--ckpt", type=int, default=0,
+                    help="weighted BP: checkpoint interval (0 = 10 for training, about sqrt(L) for evaluation)")
     ap.add_argument("--lr", type=float, default=0.01, help="weighted BP: Adam learning rate")
     ap.add_argument("--eval-frames", type=int, default=1000, help="wbp-eval: fresh frames for the FER comparison")
     ap.add_argument("--profile", default="r0.1", choices=sorted(PROFILES), help="code of --workload single")
