@@ -514,7 +514,8 @@ def run_single(args, cpu) -> dict:
     d_llr = torch.from_numpy(llr).to(dev)
     d_syn = met.syndrome(code, torch.from_numpy(bits).to(dev))
     half = args.c2v_fp16
-    q8 = args.c2v_q8
+    q8 = args.c2v_q8 or args.check_lut
+    lut = args.check_lut
     ws = torch.empty(met.workspace_bytes(code, B, args.fixed_iters, c2v_fp16=half, c2v_q8=q8) + 256,
                      dtype=torch.uint8,
                      device=dev)
@@ -523,7 +524,7 @@ def run_single(args, cpu) -> dict:
     def step():
         return met.decode(code, d_llr, d_syn, max_iter, fixed_iters=args.fixed_iters, workspace=ws,
                           check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk, c2v_fp16=half,
-                          c2v_q8=q8)
+                          c2v_q8=q8, check_lut=lut)
 
     ms_ev, kt, out = timed(step, args.steps, args.warmup)
     # throughput from a pass without the per-launch events (they cost the
@@ -559,6 +560,8 @@ def run_single(args, cpu) -> dict:
     rec["us_per_iteration"] = round(1e3 * ms / args.steps / max(1, int(out.iterations.max().item())), 2)
     if half or q8:  # the batched form stores float messages only
         rec["config"]["c2v_storage"] = "fp16" if half else "8-bit log-magnitude codes"
+        if lut:
+            rec["config"]["check_update"] = "table-driven (phi and output codes read from tables on the 8-bit grid)"
         return rec
     # the same job through the batched persistent launch (one graph replay per
     # decode), on the same inputs; outputs must be identical
@@ -891,6 +894,8 @@ def main() -> int:
                     help="single: check-to-variable messages stored in half precision (MET_C2V_FP16)")
     ap.add_argument("--c2v-q8", action="store_true",
                     help="single: check-to-variable messages stored in 8 bits (MET_C2V_Q8)")
+    ap.add_argument("--check-lut", action="store_true",
+                    help="single: 8-bit message storage with the table-driven check update (MET_CHECK_LUT)")
     ap.add_argument("--waterfall", action="store_true",
                     help="jobs at the waterfall SNRs of their rates (0.19 / 0.10 / 0.065) instead of the "
                          "workload's operating points")

@@ -75,6 +75,16 @@ extern "C" {
                                float.  A quarter of the message bytes.  Groups
                                of 64 frames only (B > 32), no compaction.
                                Gated like MET_C2V_FP16 by the frame error rate */
+#define MET_CHECK_LUT 32u   /* with MET_C2V_Q8: table-driven check update (the
+                               lookup-table form of the LLR update, last
+                               paragraph of Methods): a message input's phi
+                               is read from a 128-entry table at its grid
+                               index, an output's 8-bit code from a second
+                               table at the grid index of its phi-domain sum
+                               (checks of a compiled shape; run-time-degree
+                               checks keep the evaluated phi).  Degree-1
+                               inputs and decisions stay in float.  Gated by
+                               the frame error rate */
 #define MET_NO_DEG1_SKIP 4u /* degree-1 variable nodes take part in every
                                iteration like the others (their check messages
                                are stored and their posteriors updated; the
@@ -245,7 +255,8 @@ int met_decode_workspace_bytes(const met_code *c, int32_t B, uint32_t flags, int
  *   syn:       dev uint8   [B][M]
  *   max_iter:  >= 1
  *   flags:     MET_EARLY_EXIT or MET_FIXED_ITERS, optionally | MET_NO_COMPACT,
- *              | MET_NO_DEG1_SKIP and/or | MET_C2V_FP16 or | MET_C2V_Q8
+ *              | MET_NO_DEG1_SKIP and/or | MET_C2V_FP16 or | MET_C2V_Q8 (with
+ *              | MET_CHECK_LUT)
  *   bits:      dev uint8 [B][N] output, hard decisions at each frame's stop
  *   iters:     dev int32 [B] output, iterations run (1..max_iter)
  *   converged: dev uint8 [B] output, 1 iff H bits = syn

@@ -18,6 +18,7 @@ MET_NO_COMPACT = 2
 MET_NO_DEG1_SKIP = 4
 MET_C2V_FP16 = 8
 MET_C2V_Q8 = 16
+MET_CHECK_LUT = 32
 MET_MAX_EDGE_TYPES = 8
 MET_NOALLOC_SCRATCH_BYTES = 256 << 20
 

@@ -7,7 +7,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from ._lib import (MET_BATCH_JOB_STREAMS, MET_BATCH_JOBS_IN_TURN, MET_BATCH_KIND_STREAMS, MET_BATCH_NO_GRAPH, MET_BATCH_NO_STAGGER,
-                   MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_C2V_Q8, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
+                   MET_BATCH_PHASE_LAUNCHES, MET_C2V_FP16, MET_C2V_Q8, MET_CHECK_LUT, MET_FIXED_ITERS, MET_NO_COMPACT, MET_NO_DEG1_SKIP, check, lib,
                    met_check_class,
                    met_code_stats, met_job, met_kernel_time, met_profile, met_tuning)
 
@@ -204,7 +204,7 @@ class DecodeOutput:
 def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, posterior: bool = False,
            workspace=None, stream=None, check_steps_per_wave: int = 0, variable_chunk: int = 0,
            compact: bool = True, deg1_skip: bool = True, c2v_fp16: bool = False,
-           c2v_q8: bool = False) -> DecodeOutput:
+           c2v_q8: bool = False, check_lut: bool = False) -> DecodeOutput:
     """Decode llr float32 [B, N] against syn uint8 [B, M] (device tensors).
 
     check_steps_per_wave and variable_chunk (0 = default) select launch shapes
@@ -213,7 +213,8 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
     iterates degree-1 variable nodes like the others (MET_NO_DEG1_SKIP; equal
     results up to FP32 rounding).  c2v_fp16=True stores check-to-variable
     messages in half precision (MET_C2V_FP16; more than 32 frames), c2v_q8=True
-    in 8 bits (MET_C2V_Q8; more than 32 frames)."""
+    in 8 bits (MET_C2V_Q8; more than 32 frames); check_lut=True (with c2v_q8)
+    runs the table-driven check update (MET_CHECK_LUT)."""
     import torch
 
     b = int(llr.shape[0])
@@ -238,7 +239,7 @@ def decode(code: Code, llr, syn, max_iter: int, fixed_iters: bool = False, poste
             code.handle, llr.data_ptr(), syn.data_ptr(), b, int(max_iter),
             (MET_FIXED_ITERS if fixed_iters else 0) | (0 if compact else MET_NO_COMPACT)
             | (0 if deg1_skip else MET_NO_DEG1_SKIP) | (MET_C2V_FP16 if c2v_fp16 else 0)
-            | (MET_C2V_Q8 if c2v_q8 else 0),
+            | (MET_C2V_Q8 if c2v_q8 else 0) | (MET_CHECK_LUT if check_lut else 0),
             bits.data_ptr(), iters.data_ptr(), conv.data_ptr(),
             None if post is None else post.data_ptr(),
             ctypes.c_void_p(ws_ptr), ws_len, ctypes.byref(tuning), _stream_ptr(stream),

@@ -528,10 +528,13 @@ extern "C" int met_syndrome(const met_code *c, const uint8_t *bits, int32_t B, u
 static int validate_decode(const met_code *c, int32_t B, uint32_t flags) {
   if (!c) return fail(MET_EINVAL, "NULL code");
   if (B < 1 || B > 65535) return fail(MET_EINVAL, "B = %d outside 1..65535", B);
-  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT | MET_NO_DEG1_SKIP | MET_C2V_FP16 | MET_C2V_Q8))
+  if (flags & ~(uint32_t)(MET_FIXED_ITERS | MET_NO_COMPACT | MET_NO_DEG1_SKIP | MET_C2V_FP16 | MET_C2V_Q8 |
+                          MET_CHECK_LUT))
     return fail(MET_EINVAL, "unknown flags 0x%x", flags);
   if ((flags & MET_C2V_FP16) && (flags & MET_C2V_Q8))
     return fail(MET_EINVAL, "MET_C2V_FP16 and MET_C2V_Q8 exclude each other");
+  if ((flags & MET_CHECK_LUT) && !(flags & MET_C2V_Q8))
+    return fail(MET_EINVAL, "MET_CHECK_LUT needs MET_C2V_Q8 (its tables live on the 8-bit grid)");
   if ((flags & (MET_C2V_FP16 | MET_C2V_Q8)) && met::choose_interleave(B) != 64)
     return fail(MET_EINVAL, "reduced message storage needs groups of 64 frames (B > 32), B = %d", B);
   return MET_OK;
@@ -597,6 +600,8 @@ extern "C" int met_decode_ex(const met_code *c, const float *llr, const uint8_t 
   met::Decoder dec{c, d, pl, static_cast<char *>(workspace), (hipStream_t)stream, B, ipw, chunk};
   if (flags & MET_C2V_FP16)
     return dec.run<64, met::half_t>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
+  if (flags & MET_CHECK_LUT)
+    return dec.run<64, met::q8lut_t>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   if (flags & MET_C2V_Q8)
     return dec.run<64, met::q8_t>(llr, syn, max_iter, flags, bits, iters, converged, posterior, nullptr, 0);
   switch (W) {

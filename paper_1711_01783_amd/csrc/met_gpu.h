@@ -78,10 +78,13 @@ using half_t = _Float16;
 // read back through a 128-entry table of the grid values.
 constexpr float kQ8Lo = -14.0f, kQ8Hi = 5.0f;
 constexpr float kQ8PerOctave = 126.0f / (kQ8Hi - kQ8Lo);
+// Grid index of a magnitude m >= 0 (0 for 0 and NaN, 127 for infinity).
+__device__ __forceinline__ uint32_t q8_mag_code(float m) {
+  float t = fmaf(__builtin_amdgcn_logf(m) - kQ8Lo, kQ8PerOctave, 1.0f);  // log2 on the grid
+  return (uint32_t)fminf(fmaxf(__builtin_rintf(t), 0.0f), 127.0f);
+}
 __device__ __forceinline__ uint32_t q8_encode(float v) {
-  float t = fmaf(__builtin_amdgcn_logf(fabsf(v)) - kQ8Lo, kQ8PerOctave, 1.0f);  // log2 on the grid
-  t = fminf(fmaxf(__builtin_rintf(t), 0.0f), 127.0f);  // 0 and NaN give code 0
-  return (uint32_t)t | ((__float_as_uint(v) >> 24) & 128u);
+  return q8_mag_code(fabsf(v)) | ((__float_as_uint(v) >> 24) & 128u);
 }
 struct q8_t {
   uint8_t c;
@@ -126,6 +129,75 @@ __device__ __forceinline__ q8_t::operator float() const {
   const float m = kQ8Table.v[c & 127u];
   return (c & 128u) ? -m : m;
 }
+
+// Table-driven check update on the same grid (MET_CHECK_LUT, with 8-bit
+// storage; the lookup-table form of the update in the last Methods
+// paragraph): a message input's phi is read from phi(m_k) at its grid index
+// k, and an output's code from the code of phi(m_k) at the grid index of its
+// phi-domain sum, so neither phi nor the logarithm of the store is evaluated
+// per edge beyond the index.  The storage type q8lut_t is q8_t's codes; it
+// selects the table form in the check kernels.
+struct q8lut_t : q8_t {
+  q8lut_t() = default;
+  __device__ explicit q8lut_t(float v) : q8_t(v) {}
+};
+struct PhiTables {
+  float a[128];      // phi(m_k); phi(0) = infinity
+  uint8_t out[128];  // grid code of phi(m_k)
+};
+// ln y for y > 0 in double: y = 2^n f with f in [1, 2), ln f = 2 artanh((f-1)/(f+1))
+// by its series ((f-1)/(f+1) <= 1/3: 40 terms leave no error in double).
+constexpr double ct_ln(double y) {
+  if (y < 1.0) return -ct_ln(1.0 / y);
+  int n = 0;
+  while (y >= 2.0) {
+    y *= 0.5;
+    ++n;
+  }
+  const double z = (y - 1.0) / (y + 1.0), z2 = z * z;
+  double term = z, sum = 0.0;
+  for (int i = 0; i < 40; ++i) {
+    sum += term / (2 * i + 1);
+    term *= z2;
+  }
+  return n * 0.69314718055994530942 + 2.0 * sum;
+}
+// phi(m) = ln((1 + a) / (1 - a)) = 2 artanh(a), a = e^-m: the artanh series
+// where a <= 1/2, else the logarithm with 1 - a from the series of -expm1(-m)
+// (no cancellation for small m).
+constexpr double ct_phi(double m) {
+  const double a = q8_exp2(-m * 1.4426950408889634074);
+  if (a <= 0.5) {
+    const double a2 = a * a;
+    double term = a, sum = 0.0;
+    for (int i = 0; i < 60; ++i) {
+      sum += term / (2 * i + 1);
+      term *= a2;
+    }
+    return 2.0 * sum;
+  }
+  double t = 1.0, one_minus_a = 0.0;  // 1 - e^-m = m - m^2/2 + m^3/6 - ...
+  for (int i = 1; i < 30; ++i) {
+    t *= -m / i;
+    one_minus_a -= t;
+  }
+  return ct_ln((2.0 - one_minus_a) / one_minus_a);
+}
+constexpr PhiTables make_phi_tables() {
+  PhiTables t{};
+  t.a[0] = __builtin_huge_valf();
+  t.out[0] = 127;
+  for (int k = 1; k < 128; ++k) {
+    const double m = q8_exp2((double)kQ8Lo + (double)(k - 1) / (double)kQ8PerOctave);
+    const double ph = ct_phi(m);
+    t.a[k] = (float)ph;
+    double c = (ct_ln(ph) * 1.4426950408889634074 - (double)kQ8Lo) * (double)kQ8PerOctave + 1.0;
+    c = c < 0.0 ? 0.0 : c > 127.0 ? 127.0 : c;
+    t.out[k] = (uint8_t)(int)(c + 0.5);
+  }
+  return t;
+}
+[[maybe_unused]] static __constant__ PhiTables kPhiTables = make_phi_tables();
 
 template <typename CT>
 __device__ __forceinline__ float ld_c2v(const float *base, int64_t i) {
@@ -354,7 +426,21 @@ template <int W, int NM, int NL, int MODE, int IPW, bool PERSIST, typename CT = 
 __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const ClassArgs &c, int64_t bx, int g) {
   constexpr int D = NM + NL;
   constexpr int IPWAVE = 64 / W;
+  constexpr bool lut = std::is_same<CT, q8lut_t>::value;
   clear_next_unsat(p, bx, g);
+  [[maybe_unused]] const float *tab_a = nullptr;
+  [[maybe_unused]] const uint8_t *tab_out = nullptr;
+  if constexpr (lut) {  // the tables in LDS, before any thread of the block can leave
+    __shared__ float s_a[128];
+    __shared__ uint8_t s_out[128];
+    if (threadIdx.x < 128) {
+      s_a[threadIdx.x] = kPhiTables.a[threadIdx.x];
+      s_out[threadIdx.x] = kPhiTables.out[threadIdx.x];
+    }
+    __syncthreads();
+    tab_a = s_a;
+    tab_out = s_out;
+  }
   const uint64_t act = p.active[g];  // not written during check updates
   if (act == 0ull) return;
   const int lane = threadIdx.x & 63, wv = wave_id();
@@ -405,7 +491,10 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     for (int m = 0; m < NM; ++m) {
       parity ^= (uint32_t)(pv[k][m] < 0.0f);
       const float x = clamp_llr(pv[k][m] - cv[k][m]);
-      A[m] = phi(fabsf(x));
+      if constexpr (lut)
+        A[m] = tab_a[q8_mag_code(fabsf(x))];
+      else
+        A[m] = phi(fabsf(x));
       neg |= sign_bit(x) << m;
     }
 #pragma unroll
@@ -432,12 +521,17 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     const bool store = valid[k] && lane_act;
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-      const float mag = phi(S[m]);
-      float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
-      if (weighted)
-        out *= edge_scale<W>(p.weights, p.wstride, p.it - 1, p.edge_type, c.first_msg, NM, m, base + k * IPWAVE,
-                             c.n_checks, q, m0 + m);
-      if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
+      if constexpr (lut) {
+        const uint32_t code = tab_out[q8_mag_code(S[m])] | (((tot ^ (neg >> m)) & 1u) << 7);
+        if (store) reinterpret_cast<uint8_t *>(p.c2v)[((int64_t)g * p.E12 + m0 + m) * W + w] = (uint8_t)code;
+      } else {
+        const float mag = phi(S[m]);
+        float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
+        if (weighted)
+          out *= edge_scale<W>(p.weights, p.wstride, p.it - 1, p.edge_type, c.first_msg, NM, m, base + k * IPWAVE,
+                               c.n_checks, q, m0 + m);
+        if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
+      }
     }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {

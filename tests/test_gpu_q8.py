@@ -11,7 +11,9 @@ oracle's in its own.  Exact properties of the storage path: the converged flag
 is the exact syndrome test of the returned bits; degree-1 posteriors after
 iteration 1, formed in float inside the check update, equal the float
 decoder's; frames well above threshold decode to the sent words; two runs are
-bit-identical.
+bit-identical.  The table-driven check update (MET_CHECK_LUT: phi of an input
+and the code of an output read from tables on the same grid) is gated the same
+way.
 """
 import json
 import math
@@ -46,9 +48,10 @@ def wilson(k, n, z=1.96):
     return c - h, c + h
 
 
+@pytest.mark.parametrize("lut", [False, True])
 @pytest.mark.parametrize("construction", ["random", "peg"])
 @pytest.mark.parametrize("prof", ["r0.1", "r0.05", "r0.02"])
-def test_q8_messages_fer_within_oracle_interval(prof, construction):
+def test_q8_messages_fer_within_oracle_interval(prof, construction, lut):
     stem = "fer_peg_%s_N65536.json" if construction == "peg" else "fer_%s_N65536.json"
     with open(os.path.join(GOLDEN, stem % prof)) as f:
         gold = json.load(f)
@@ -62,8 +65,9 @@ def test_q8_messages_fer_within_oracle_interval(prof, construction):
     code_o = oc.from_edges(n, code.M, vn, cn, et, n_edge_types=3)
     bits, llr = make_frames(n, b, gold["snr"], gold["frame_seed"])
     syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
-    print("FER with 8-bit messages", construction, prof, n, b, gold["snr"], flush=True)
-    out = met.decode(code, torch.from_numpy(llr).to(DEV), syn, gold["max_iter"], c2v_q8=True)
+    print("FER with 8-bit messages", "table-driven check update" if lut else "", construction, prof, n, b,
+          gold["snr"], flush=True)
+    out = met.decode(code, torch.from_numpy(llr).to(DEV), syn, gold["max_iter"], c2v_q8=True, check_lut=lut)
     torch.cuda.synchronize()
     got = out.bits.cpu().numpy()
     conv = out.converged.cpu().numpy()
@@ -106,8 +110,34 @@ def test_q8_first_iteration_and_determinism(prof, n, b, snr):
         np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
 
 
+def test_lut_check_update_is_deterministic_and_differs_from_evaluated_phi():
+    code = met.Code.build(PROFILES["r0.05"], 8192, 6)
+    bits, llr = make_frames(8192, 64, 0.10, 12)
+    d_llr = torch.from_numpy(llr).to(DEV)
+    syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
+    a = met.decode(code, d_llr, syn, 30, c2v_q8=True, check_lut=True)
+    b = met.decode(code, d_llr, syn, 30, c2v_q8=True, check_lut=True)
+    e = met.decode(code, d_llr, syn, 2, fixed_iters=True, posterior=True, c2v_q8=True)
+    t = met.decode(code, d_llr, syn, 2, fixed_iters=True, posterior=True, c2v_q8=True, check_lut=True)
+    torch.cuda.synchronize()
+    for x, y in ((a.bits, b.bits), (a.iterations, b.iterations), (a.converged, b.converged)):
+        np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+    pe, pt = e.posterior.cpu().numpy(), t.posterior.cpu().numpy()
+    assert np.any(pe != pt)  # the tables really replace phi
+    # both are approximations of the same update: the posteriors agree in sign
+    # on nearly every bit after two iterations
+    assert np.mean(np.sign(pe) == np.sign(pt)) > 0.97
+    s = syn.cpu().numpy()
+    from oracle import code as oc2
+    vn, cn, et = code.export()
+    code_o = oc2.from_edges(8192, code.M, vn, cn, et, n_edge_types=3)
+    np.testing.assert_array_equal(a.converged.cpu().numpy(),
+                                  np.all(oc2.syndrome(code_o, a.bits.cpu().numpy()) == s, axis=1).astype(np.uint8))
+
+
+@pytest.mark.parametrize("lut", [False, True])
 @pytest.mark.parametrize("snr", [0.3, 0.4])
-def test_q8_decodes_clean_frames(snr):
+def test_q8_decodes_clean_frames(snr, lut):
     """Above the waterfall the 8-bit storage decodes every frame that float
     storage decodes, to the sent word (at SNR 0.3 one of these 40 frames is
     stuck for both)."""
@@ -116,7 +146,7 @@ def test_q8_decodes_clean_frames(snr):
     syn = met.syndrome(code, torch.from_numpy(bits).to(DEV))
     d_llr = torch.from_numpy(llr).to(DEV)
     ref = met.decode(code, d_llr, syn, 60)
-    out = met.decode(code, d_llr, syn, 60, c2v_q8=True)
+    out = met.decode(code, d_llr, syn, 60, c2v_q8=True, check_lut=lut)
     torch.cuda.synchronize()
     ok = ref.converged.cpu().numpy() == 1
     assert ok.sum() >= 39

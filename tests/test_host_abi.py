@@ -140,8 +140,10 @@ def test_decode_argument_validation_without_gpu():
     assert call(llr=P(258)) == -1          # misaligned float buffer
     assert call(ws=P(264)) == -1           # workspace not 256-byte aligned
     assert call(wsb=big - 1) == -1         # too small
-    assert call(flags=32) == -1
+    assert call(flags=64) == -1            # first unknown flag
     assert "flags" in L.met_last_error().decode()
+    assert call(flags=_lib.MET_CHECK_LUT) == -1   # the table-driven update needs 8-bit storage
+    assert "MET_C2V_Q8" in L.met_last_error().decode()
     assert call(flags=4) == -1             # the all-VN layout needs a larger workspace
     assert "workspace" in L.met_last_error().decode()
     assert L.met_syndrome(c.handle, None, 1, dummy, None) == -1
