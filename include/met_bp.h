@@ -78,9 +78,10 @@ extern "C" {
 #define MET_CHECK_LUT 32u   /* with MET_C2V_Q8: table-driven check update (the
                                lookup-table form of the LLR update, last
                                paragraph of Methods): a message input's phi
-                               is read from a 128-entry table at its grid
-                               index, an output's 8-bit code from a second
-                               table at the grid index of its phi-domain sum
+                               is read from a 512-entry table at the index of
+                               its magnitude on a grid 4x finer than the
+                               storage grid, an output's 8-bit code from a
+                               second table at the index of its phi-domain sum
                                (checks of a compiled shape; run-time-degree
                                checks keep the evaluated phi).  Degree-1
                                inputs and decisions stay in float.  Gated by

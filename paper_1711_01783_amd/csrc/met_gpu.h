@@ -130,20 +130,28 @@ __device__ __forceinline__ q8_t::operator float() const {
   return (c & 128u) ? -m : m;
 }
 
-// Table-driven check update on the same grid (MET_CHECK_LUT, with 8-bit
-// storage; the lookup-table form of the update in the last Methods
-// paragraph): a message input's phi is read from phi(m_k) at its grid index
-// k, and an output's code from the code of phi(m_k) at the grid index of its
-// phi-domain sum, so neither phi nor the logarithm of the store is evaluated
-// per edge beyond the index.  The storage type q8lut_t is q8_t's codes; it
-// selects the table form in the check kernels.
+// Table-driven check update (MET_CHECK_LUT, with 8-bit storage; the
+// lookup-table form of the update in the last Methods paragraph): a message
+// input's phi is read from a table at the index of its magnitude on a grid
+// kLutSub times finer than the storage grid, and an output's 8-bit code from a
+// second table at the fine index of its phi-domain sum, so neither phi nor the
+// logarithm of the store is evaluated per edge beyond the index.  Fine index
+// i >= 1 stands for m_i = 2^(kQ8Lo + (i - kLutSub) / (kLutSub kQ8PerOctave))
+// (i = kLutSub k is the storage grid's m_k), i = 0 for 0: 1.3 % rounding at
+// most on either side.  The storage type q8lut_t is q8_t's codes; it selects
+// the table form in the check kernels.
 struct q8lut_t : q8_t {
   q8lut_t() = default;
   __device__ explicit q8lut_t(float v) : q8_t(v) {}
 };
+constexpr int kLutSub = 4, kLutSize = 128 * kLutSub;
+__device__ __forceinline__ uint32_t lut_index(float m) {
+  float t = fmaf(__builtin_amdgcn_logf(m) - kQ8Lo, kQ8PerOctave * kLutSub, (float)kLutSub);
+  return (uint32_t)fminf(fmaxf(__builtin_rintf(t), 0.0f), (float)(kLutSize - 1));
+}
 struct PhiTables {
-  float a[128];      // phi(m_k); phi(0) = infinity
-  uint8_t out[128];  // grid code of phi(m_k)
+  float a[kLutSize];      // phi(m_i); phi(0) = infinity
+  uint8_t out[kLutSize];  // storage code of phi(m_i)
 };
 // ln y for y > 0 in double: y = 2^n f with f in [1, 2), ln f = 2 artanh((f-1)/(f+1))
 // by its series ((f-1)/(f+1) <= 1/3: 40 terms leave no error in double).
@@ -187,8 +195,8 @@ constexpr PhiTables make_phi_tables() {
   PhiTables t{};
   t.a[0] = __builtin_huge_valf();
   t.out[0] = 127;
-  for (int k = 1; k < 128; ++k) {
-    const double m = q8_exp2((double)kQ8Lo + (double)(k - 1) / (double)kQ8PerOctave);
+  for (int k = 1; k < kLutSize; ++k) {
+    const double m = q8_exp2((double)kQ8Lo + (double)(k - kLutSub) / ((double)kQ8PerOctave * kLutSub));
     const double ph = ct_phi(m);
     t.a[k] = (float)ph;
     double c = (ct_ln(ph) * 1.4426950408889634074 - (double)kQ8Lo) * (double)kQ8PerOctave + 1.0;
@@ -431,11 +439,11 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
   [[maybe_unused]] const float *tab_a = nullptr;
   [[maybe_unused]] const uint8_t *tab_out = nullptr;
   if constexpr (lut) {  // the tables in LDS, before any thread of the block can leave
-    __shared__ float s_a[128];
-    __shared__ uint8_t s_out[128];
-    if (threadIdx.x < 128) {
-      s_a[threadIdx.x] = kPhiTables.a[threadIdx.x];
-      s_out[threadIdx.x] = kPhiTables.out[threadIdx.x];
+    __shared__ float s_a[kLutSize];
+    __shared__ uint8_t s_out[kLutSize];
+    for (int i = threadIdx.x; i < kLutSize; i += kBlock) {
+      s_a[i] = kPhiTables.a[i];
+      s_out[i] = kPhiTables.out[i];
     }
     __syncthreads();
     tab_a = s_a;
@@ -492,7 +500,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
       parity ^= (uint32_t)(pv[k][m] < 0.0f);
       const float x = clamp_llr(pv[k][m] - cv[k][m]);
       if constexpr (lut)
-        A[m] = tab_a[q8_mag_code(fabsf(x))];
+        A[m] = tab_a[lut_index(fabsf(x))];
       else
         A[m] = phi(fabsf(x));
       neg |= sign_bit(x) << m;
@@ -522,7 +530,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
       if constexpr (lut) {
-        const uint32_t code = tab_out[q8_mag_code(S[m])] | (((tot ^ (neg >> m)) & 1u) << 7);
+        const uint32_t code = tab_out[lut_index(S[m])] | (((tot ^ (neg >> m)) & 1u) << 7);
         if (store) reinterpret_cast<uint8_t *>(p.c2v)[((int64_t)g * p.E12 + m0 + m) * W + w] = (uint8_t)code;
       } else {
         const float mag = phi(S[m]);
