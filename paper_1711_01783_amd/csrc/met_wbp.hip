@@ -26,8 +26,9 @@
 //        A_e' + r_ee' is the leave-one-out sum of e.
 //   vbar_e' = xbar_e' where the clamp is inactive, else 0
 //   Cbar^{l-1}_e' = -vbar_e',   Pbar^{l-1}_v = sum_{e in E(v)} vbar_e.
-// Each segment between checkpoints is recomputed forward before its reverse
-// pass.  All reductions run in a fixed order (deterministic gradients).
+// Each segment between checkpoints but the last (whose states the forward pass
+// leaves in the segment slots) is recomputed forward before its reverse pass.
+// All reductions run in a fixed order (deterministic gradients).
 #include "met_gpu.h"
 
 namespace met {
@@ -492,9 +493,12 @@ struct Wbp {
     if (!bits) bits = at<uint8_t>(pl.off_bits);
     if (!conv) conv = at<uint8_t>(pl.off_conv);
     init<W>(llr, syn, iters, conv);
+    // the last segment's states go straight to the segment slots, where the
+    // reverse sweep needs them (it recomputes the other segments only)
+    const int a_last = (pl.L - 1) / pl.k * pl.k;
     State prev{nullptr, nullptr};
     for (int l = 1; l <= pl.L; ++l) {
-      const State out = (l % pl.k == 0 && l < pl.L) ? ckpt(l) : work(l);
+      const State out = (l % pl.k == 0 && l < pl.L) ? ckpt(l) : (l > a_last && l < pl.L) ? seg(l - a_last) : work(l);
       iterate<W>(l, prev, out, l == pl.L);
       prev = out;
     }
@@ -608,9 +612,10 @@ struct Wbp {
     const int nsegs = (pl.L + pl.k - 1) / pl.k;
     for (int sg = nsegs - 1; sg >= 0; --sg) {
       const int a = sg * pl.k, bnd = std::min(a + pl.k, pl.L);
-      // recompute states a+1 .. bnd-1 from the checkpoint at a
+      // recompute states a+1 .. bnd-1 from the checkpoint at a (the last
+      // segment's are still in the segment slots from the forward pass)
       State prev = a == 0 ? State{nullptr, nullptr} : ckpt(a);
-      for (int l = a + 1; l < bnd; ++l) {
+      for (int l = a + 1; l < bnd && sg < nsegs - 1; ++l) {
         const State out = seg(l - a);
         iterate<W>(l, prev, out, false);
         prev = out;
