@@ -397,13 +397,16 @@ int met_decode_ex(const met_code *c, const float *llr, const uint8_t *syn, int32
 
 /* ---- Batched decoding ------------------------------------------------------
  * Several decode jobs -- possibly different codes (rates), batch sizes and
- * iteration budgets -- in one persistent kernel launch whose iterations of all
- * jobs are interleaved (captured with its set-up and output kernels in one HIP
- * graph, cached per configuration).  Each job's results are identical to
- * met_decode's for the same inputs (the same kernels decode them, with groups
- * of 64 frames).  The launch is persistent: its grid is sized to be resident
- * at once and steps through the iterations of all jobs with a grid-wide
- * barrier between phases.  Batches holding codes with check degrees that have
+ * iteration budgets -- in one HIP graph (set-up, iterations, outputs; cached
+ * per configuration) whose iterations of all jobs are interleaved phase by
+ * phase.  Each job's results are identical to met_decode's for the same
+ * inputs (the same tile bodies decode them).  The iterations run as one
+ * persistent launch (the default; its grid is sized to be resident at once
+ * and steps through the phases of all jobs with a grid-wide barrier between
+ * them) or as one launch per phase (MET_BATCH_PHASE_LAUNCHES and the stream
+ * modes below); met_batched_autotune picks among them.  Where a job's (3,1) /
+ * (2,1) check classes fill the GPU on their own, the phase schedules launch
+ * them with the plain decoder's check kernel.  Batches holding codes with check degrees that have
  * no compiled shape run their check tiles with one step per wave, except the
  * (3,1) / (2,1) checks where the schedule gives them launches of their own
  * (phase launches without stagger, or on parallel streams). */
