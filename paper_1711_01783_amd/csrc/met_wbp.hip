@@ -165,21 +165,26 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
 #pragma unroll UNR
     for (int e = 0; e < D; ++e)
       Qd[e] = e < nm + nl ? Q[e] * __builtin_amdgcn_rcpf(expm1_nonpos(-2.0f * (pre[e] + suf[e]))) : 0.0f;
+    // e^{-r_ek} for the leave-two-out sums r_ek (A over the inputs other than
+    // e and k) as products of the inputs' e^{-A}: one exponential per input
+    // instead of one per (source, target) pair
+    float E[D];
+#pragma unroll UNR
+    for (int o = 0; o < D; ++o) E[o] = __expf(-A[o]);  // absent inputs: A = 0, E = 1
 #pragma unroll UNR
     for (int k = 0; k < D; ++k) {
       if (k >= nm) continue;
-      // leave-two-out sums r_ek = sum of A over inputs other than e and k
       float pb[D], sb[D];
-      pb[0] = 0.0f;
+      pb[0] = 1.0f;
 #pragma unroll UNR
-      for (int o = 1; o < D; ++o) pb[o] = pb[o - 1] + (o - 1 == k ? 0.0f : A[o - 1]);
-      sb[D - 1] = 0.0f;
+      for (int o = 1; o < D; ++o) pb[o] = pb[o - 1] * (o - 1 == k ? 1.0f : E[o - 1]);
+      sb[D - 1] = 1.0f;
 #pragma unroll UNR
-      for (int o = D - 2; o >= 0; --o) sb[o] = sb[o + 1] + (o + 1 == k ? 0.0f : A[o + 1]);
+      for (int o = D - 2; o >= 0; --o) sb[o] = sb[o + 1] * (o + 1 == k ? 1.0f : E[o + 1]);
       float xs = 0.0f;
 #pragma unroll UNR
       for (int e = 0; e < D; ++e)
-        if (e != k && e < nm + nl) xs += Qd[e] * __expf(-(pb[e] + sb[e]));
+        if (e != k && e < nm + nl) xs += Qd[e] * (pb[e] * sb[e]);
       float xb = expm1_nonpos(-2.0f * A[k]) * xs;
       if ((neg >> k) & 1u) xb = -xb;
       const float vbar = ((inrange >> k) & 1u) ? xb : 0.0f;
