@@ -157,6 +157,7 @@ def cpu_baseline(jobs, n: int, snr, sample_iters: int, max_workers: int) -> dict
         "unit": "Mbit/s",
         "cores": workers,
         "kind": "oracle",
+        "extrapolated": True,  # from the timed sample below to the whole workload, not a timed full decode
         "sample": "%d frames (one per core: %s), %d iterations each in fixed mode; the slowest frame's time per "
         "iteration of each code, times frames x budget of the workload, spread over %d cores (wall %.1f s)"
         % (workers, ", ".join("%d of %s" % (sum(1 for t in tasks if t[0] == p), p) for p, _, _ in jobs),

@@ -327,3 +327,12 @@ def test_q8_messages_flag():
     assert L.met_decode_workspace_bytes(c.handle, 20, _lib.MET_C2V_Q8, 0, ctypes.byref(n)) == -1   # W < 64
     assert L.met_decode_workspace_bytes(c.handle, 64, _lib.MET_C2V_Q8 | _lib.MET_C2V_FP16, 0,
                                         ctypes.byref(n)) == -1
+
+
+def test_batched_decoder_rejects_unknown_stream_modes():
+    with pytest.raises(ValueError, match="streams"):
+        met.BatchedDecoder(streams="parallel")
+    for mode, flag in (("one", 0), ("kinds", _lib.MET_BATCH_KIND_STREAMS), ("jobs", _lib.MET_BATCH_JOB_STREAMS),
+                       ("serial", _lib.MET_BATCH_JOBS_IN_TURN)):
+        d = met.BatchedDecoder(streams=mode, stagger=False)
+        assert d.tuning.batch_flags == flag | _lib.MET_BATCH_NO_STAGGER
