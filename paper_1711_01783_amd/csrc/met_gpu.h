@@ -207,13 +207,32 @@ constexpr PhiTables make_phi_tables() {
 }
 [[maybe_unused]] static __constant__ PhiTables kPhiTables = make_phi_tables();
 
+// Message rows are streamed: each kernel reads (and the check update writes)
+// every row once, so their loads and stores carry the non-temporal hint,
+// which keeps them from displacing the rows that are reused (the gathered
+// posteriors) in the caches.
+template <typename CT>
+__device__ __forceinline__ float ld_msg(const CT *p) {
+  if constexpr (std::is_class<CT>::value) {  // 8-bit codes: their byte
+    CT r;
+    r.c = __builtin_nontemporal_load(reinterpret_cast<const uint8_t *>(p));
+    return (float)r;
+  } else {
+    return (float)__builtin_nontemporal_load(p);
+  }
+}
 template <typename CT>
 __device__ __forceinline__ float ld_c2v(const float *base, int64_t i) {
-  return (float)reinterpret_cast<const CT *>(base)[i];
+  return ld_msg<CT>(reinterpret_cast<const CT *>(base) + i);
 }
 template <typename CT>
 __device__ __forceinline__ void st_c2v(float *base, int64_t i, float v) {
-  reinterpret_cast<CT *>(base)[i] = (CT)v;
+  if constexpr (std::is_class<CT>::value) {
+    const CT q(v);
+    __builtin_nontemporal_store(q.c, reinterpret_cast<uint8_t *>(base) + i);
+  } else {
+    __builtin_nontemporal_store((CT)v, reinterpret_cast<CT *>(base) + i);
+  }
 }
 
 enum : int32_t {
@@ -484,7 +503,7 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      lf[k][l] = p.Lphi[((int64_t)g * p.EL + l0 + l) * W + w];
+      lf[k][l] = __builtin_nontemporal_load(&p.Lphi[((int64_t)g * p.EL + l0 + l) * W + w]);
       b1[k][l] = test ? ld_word<PERSIST>(p.B1in, (int64_t)g * p.EL + l0 + l) : 0ull;
     }
   }
@@ -531,7 +550,8 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     for (int m = 0; m < NM; ++m) {
       if constexpr (lut) {
         const uint32_t code = tab_out[lut_index(S[m])] | (((tot ^ (neg >> m)) & 1u) << 7);
-        if (store) reinterpret_cast<uint8_t *>(p.c2v)[((int64_t)g * p.E12 + m0 + m) * W + w] = (uint8_t)code;
+        if (store)
+          __builtin_nontemporal_store((uint8_t)code, reinterpret_cast<uint8_t *>(p.c2v) + ((int64_t)g * p.E12 + m0 + m) * W + w);
       } else {
         const float mag = phi(S[m]);
         float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
@@ -777,7 +797,7 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
   for (; e + U <= e1; e += U) {
     float a[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) a[u] = (float)c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
+    for (int u = 0; u < U; ++u) a[u] = ld_msg<CT>(c2v + (int64_t)ldro(p.vn_edges, e + u) * W);
 #pragma unroll
     for (int u = 0; u < U; ++u) P += a[u];
   }
@@ -785,11 +805,11 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
     for (; e + 8 <= e1; e += 8) {
       float a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = (float)c2v[(int64_t)ldro(p.vn_edges, e + u) * W];
+      for (int u = 0; u < 8; ++u) a[u] = ld_msg<CT>(c2v + (int64_t)ldro(p.vn_edges, e + u) * W);
 #pragma unroll
       for (int u = 0; u < 8; ++u) P += a[u];
     }
-  for (; e < e1; ++e) P += (float)c2v[(int64_t)ldro(p.vn_edges, e) * W];
+  for (; e < e1; ++e) P += ld_msg<CT>(c2v + (int64_t)ldro(p.vn_edges, e) * W);
   if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
 }
 
