@@ -96,6 +96,12 @@ def _load():
         raise ImportError(
             "libmetbp.so is not built (expected at %s); run `python paper_1711_01783_amd/build.py`" % library_path
         )
+    # The library and PyTorch must run on one HIP runtime: PyTorch's is loaded
+    # first, so that the library's libamdhip64 dependency resolves to the
+    # runtime already in the process (loaded the other way round, the library
+    # finds no device).
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(library_path)
     P = ctypes.c_void_p
     i32, i64, u32, u64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
