@@ -208,30 +208,50 @@ constexpr PhiTables make_phi_tables() {
 [[maybe_unused]] static __constant__ PhiTables kPhiTables = make_phi_tables();
 
 // Message rows are streamed: each kernel reads (and the check update writes)
-// every row once, so their loads and stores carry the non-temporal hint,
-// which keeps them from displacing the rows that are reused (the gathered
-// posteriors) in the caches.
-template <typename CT>
+// every row once, so rows of 256 bytes (64 frames per item, float messages)
+// are loaded and stored with the non-temporal hint, which keeps them from
+// displacing the rows that are reused (the gathered posteriors) in the
+// caches.  Shorter rows (16 or 32 frames per item, 16-bit or 8-bit messages)
+// share a 128-byte line with their neighbours, and the decodes that use 16 or
+// 32 frames per item mostly fit in the Infinity Cache: there the hint made
+// the decoders slower, and such rows are loaded and stored plainly.
+template <int W, typename T>
+constexpr bool kStreamRows = W * sizeof(T) >= 256;
+template <int W, typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  if constexpr (kStreamRows<W, T>)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <int W, typename T>
+__device__ __forceinline__ void st_stream(T v, T *p) {
+  if constexpr (kStreamRows<W, T>)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+template <int W, typename CT>
 __device__ __forceinline__ float ld_msg(const CT *p) {
   if constexpr (std::is_class<CT>::value) {  // 8-bit codes: their byte
     CT r;
-    r.c = __builtin_nontemporal_load(reinterpret_cast<const uint8_t *>(p));
+    r.c = ld_stream<W>(reinterpret_cast<const uint8_t *>(p));
     return (float)r;
   } else {
-    return (float)__builtin_nontemporal_load(p);
+    return (float)ld_stream<W>(p);
   }
 }
-template <typename CT>
+template <int W, typename CT>
 __device__ __forceinline__ float ld_c2v(const float *base, int64_t i) {
-  return ld_msg<CT>(reinterpret_cast<const CT *>(base) + i);
+  return ld_msg<W, CT>(reinterpret_cast<const CT *>(base) + i);
 }
-template <typename CT>
+template <int W, typename CT>
 __device__ __forceinline__ void st_c2v(float *base, int64_t i, float v) {
   if constexpr (std::is_class<CT>::value) {
     const CT q(v);
-    __builtin_nontemporal_store(q.c, reinterpret_cast<uint8_t *>(base) + i);
+    st_stream<W>(q.c, reinterpret_cast<uint8_t *>(base) + i);
   } else {
-    __builtin_nontemporal_store((CT)v, reinterpret_cast<CT *>(base) + i);
+    st_stream<W>((CT)v, reinterpret_cast<CT *>(base) + i);
   }
 }
 
@@ -499,11 +519,11 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
     for (int m = 0; m < NM; ++m) {
       const int32_t vi = ldro(p.edge_msgvn, m0 + m);
       pv[k][m] = p.Pin[((int64_t)g * p.N2 + vi) * W + w];
-      cv[k][m] = first ? 0.0f : ld_c2v<CT>(p.c2v_in, ((int64_t)g * p.E12 + m0 + m) * W + w);
+      cv[k][m] = first ? 0.0f : ld_c2v<W, CT>(p.c2v_in, ((int64_t)g * p.E12 + m0 + m) * W + w);
     }
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
-      lf[k][l] = __builtin_nontemporal_load(&p.Lphi[((int64_t)g * p.EL + l0 + l) * W + w]);
+      lf[k][l] = ld_stream<W>(&p.Lphi[((int64_t)g * p.EL + l0 + l) * W + w]);
       b1[k][l] = test ? ld_word<PERSIST>(p.B1in, (int64_t)g * p.EL + l0 + l) : 0ull;
     }
   }
@@ -551,14 +571,14 @@ __device__ __forceinline__ void check_fixed_body(const CheckParams &p, const Cla
       if constexpr (lut) {
         const uint32_t code = tab_out[lut_index(S[m])] | (((tot ^ (neg >> m)) & 1u) << 7);
         if (store)
-          __builtin_nontemporal_store((uint8_t)code, reinterpret_cast<uint8_t *>(p.c2v) + ((int64_t)g * p.E12 + m0 + m) * W + w);
+          st_stream<W>((uint8_t)code, reinterpret_cast<uint8_t *>(p.c2v) + ((int64_t)g * p.E12 + m0 + m) * W + w);
       } else {
         const float mag = phi(S[m]);
         float out = ((tot ^ (neg >> m)) & 1u) ? -mag : mag;
         if (weighted)
           out *= edge_scale<W>(p.weights, p.wstride, p.it - 1, p.edge_type, c.first_msg, NM, m, base + k * IPWAVE,
                                c.n_checks, q, m0 + m);
-        if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
+        if (store) st_c2v<W, CT>(p.c2v, ((int64_t)g * p.E12 + m0 + m) * W + w, out);
       }
     }
 #pragma unroll
@@ -628,7 +648,7 @@ __device__ __forceinline__ void check_generic_body(const CheckParams &p, const C
     if (k < nm) {
       const int64_t e = m0 + k;
       const float pv = p.Pin[((int64_t)g * p.N2 + p.edge_msgvn[e]) * W + w];
-      const float cv = first ? 0.0f : ld_c2v<CT>(p.c2v_in, ((int64_t)g * p.E12 + e) * W + w);
+      const float cv = first ? 0.0f : ld_c2v<W, CT>(p.c2v_in, ((int64_t)g * p.E12 + e) * W + w);
       parity ^= (uint32_t)(pv < 0.0f);
       const float x = clamp_llr(pv - cv);
       A[k] = phi(fabsf(x));
@@ -657,7 +677,7 @@ __device__ __forceinline__ void check_generic_body(const CheckParams &p, const C
       const float mag = phi(pre[k] + suf[k]);
       float out = ((tot ^ (neg >> k)) & 1u) ? -mag : mag;
       if (weighted) out *= p.weights[(int64_t)p.edge_type[m0 + k] * p.wstride + (p.it - 1)];
-      if (store) st_c2v<CT>(p.c2v, ((int64_t)g * p.E12 + m0 + k) * W + w, out);
+      if (store) st_c2v<W, CT>(p.c2v, ((int64_t)g * p.E12 + m0 + k) * W + w, out);
     }
   }
   // Leaf decisions: ballots must be executed by every lane of the wave, so the
@@ -797,7 +817,7 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
   for (; e + U <= e1; e += U) {
     float a[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) a[u] = ld_msg<CT>(c2v + (int64_t)ldro(p.vn_edges, e + u) * W);
+    for (int u = 0; u < U; ++u) a[u] = ld_msg<W, CT>(c2v + (int64_t)ldro(p.vn_edges, e + u) * W);
 #pragma unroll
     for (int u = 0; u < U; ++u) P += a[u];
   }
@@ -805,11 +825,11 @@ __device__ __forceinline__ void variable_body(const VarParams &p, int64_t bx, in
     for (; e + 8 <= e1; e += 8) {
       float a[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = ld_msg<CT>(c2v + (int64_t)ldro(p.vn_edges, e + u) * W);
+      for (int u = 0; u < 8; ++u) a[u] = ld_msg<W, CT>(c2v + (int64_t)ldro(p.vn_edges, e + u) * W);
 #pragma unroll
       for (int u = 0; u < 8; ++u) P += a[u];
     }
-  for (; e < e1; ++e) P += ld_msg<CT>(c2v + (int64_t)ldro(p.vn_edges, e) * W);
+  for (; e < e1; ++e) P += ld_msg<W, CT>(c2v + (int64_t)ldro(p.vn_edges, e) * W);
   if (lane_act) p.P[((int64_t)g * p.N2 + i) * W + w] = P;
 }
 

@@ -113,14 +113,14 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
       const int64_t e = m0 + k;
       const int32_t vi = p.edge_msgvn[e];
       const float pv = p.Pin[((int64_t)g * p.N2 + vi) * W + w];
-      const float cv = p.first ? 0.0f : __builtin_nontemporal_load(&p.c2v_in[((int64_t)g * p.E12 + e) * W + w]);
+      const float cv = p.first ? 0.0f : ld_stream<W>(&p.c2v_in[((int64_t)g * p.E12 + e) * W + w]);
       const float v = pv - cv;
       inrange |= (uint32_t)(fabsf(v) < kLlrMax) << k;
       const float x = clamp_llr(v);
       A[k] = phi(fabsf(x));
       neg |= sign_bit(x) << k;
       gsum[k] = p.Pbar[((int64_t)g * p.N2 + vi) * W + w] +
-                __builtin_nontemporal_load(&p.Cbar[((int64_t)g * p.E12 + e) * W + w]);
+                ld_stream<W>(&p.Cbar[((int64_t)g * p.E12 + e) * W + w]);
       ty[k] = (int8_t)edge_type_of<W>(p.edge_type, e);
     } else if (k < nm + nl) {
       const int64_t le = l0 + (k - nm);
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_check_adj(const AdjParams p, const C
       float xb = expm1_nonpos(-2.0f * A[k]) * xs;
       if ((neg >> k) & 1u) xb = -xb;
       const float vbar = ((inrange >> k) & 1u) ? xb : 0.0f;
-      if (valid) __builtin_nontemporal_store(-vbar, &p.Cbar[((int64_t)g * p.E12 + m0 + k) * W + w]);
+      if (valid) st_stream<W>(-vbar, &p.Cbar[((int64_t)g * p.E12 + m0 + k) * W + w]);
     }
   }
   // block sums of dLoss/dw, in a fixed order.  Wave sums of all types at
@@ -245,26 +245,26 @@ __global__ __launch_bounds__(kBlock) void k_variable_adj(const VarAdjParams p) {
   for (; e + 8 <= e1; e += 8) {
     float a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(cb + (int64_t)ldro(p.vn_edges, e + u) * W);
+    for (int u = 0; u < 8; ++u) a[u] = ld_stream<W>(cb + (int64_t)ldro(p.vn_edges, e + u) * W);
 #pragma unroll
     for (int u = 0; u < 8; ++u) s += a[u];
   }
   if (e + 4 <= e1) {
     float a[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = __builtin_nontemporal_load(cb + (int64_t)ldro(p.vn_edges, e + u) * W);
+    for (int u = 0; u < 4; ++u) a[u] = ld_stream<W>(cb + (int64_t)ldro(p.vn_edges, e + u) * W);
 #pragma unroll
     for (int u = 0; u < 4; ++u) s += a[u];
     e += 4;
   }
   if (e + 2 <= e1) {
-    const float a0 = __builtin_nontemporal_load(cb + (int64_t)ldro(p.vn_edges, e) * W),
-                a1 = __builtin_nontemporal_load(cb + (int64_t)ldro(p.vn_edges, e + 1) * W);
+    const float a0 = ld_stream<W>(cb + (int64_t)ldro(p.vn_edges, e) * W),
+                a1 = ld_stream<W>(cb + (int64_t)ldro(p.vn_edges, e + 1) * W);
     s += a0;
     s += a1;
     e += 2;
   }
-  if (e < e1) s += __builtin_nontemporal_load(cb + (int64_t)ldro(p.vn_edges, e) * W);
+  if (e < e1) s += ld_stream<W>(cb + (int64_t)ldro(p.vn_edges, e) * W);
   p.Pbar[((int64_t)g * p.N2 + i) * W + w] = -s;
 }
 
