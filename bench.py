@@ -49,7 +49,7 @@ CODE_SEED = {"r0.1": 101, "r0.05": 102, "r0.02": 103}
 FRAME_SEED = 5000
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 MIX = ("r0.1", "r0.05", "r0.02")
-KERNEL_SOURCES = ("met_gpu.h", "met_decode.hip", "met_batched.hip")
+KERNEL_SOURCES = ("met_gpu.h", "met_decode.hip", "met_batched.hip", "met_code.cpp")  # kernels and the layout they read
 
 
 def class_bytes_per_frame(cls: dict, W: int, first: bool = False, test: bool = True, cb: int = 4) -> float:
