@@ -368,6 +368,12 @@ def run_mix(args, cpu) -> dict:
                            check_steps_per_wave=args.check_steps, variable_chunk=args.vn_chunk)
                 for j, w in zip(jobs, wss)]
 
+    if args.plain_only:  # profiling runs of the plain form's launches alone
+        for _ in range(args.warmup + args.steps):
+            plain()
+        torch.cuda.synchronize()
+        return {"plain_only": True, "steps": args.steps, "warmup": args.warmup}
+
     # plain form: per-launch timing (for its roofline) adds two events to each of
     # its ~2000 launches per step, so its throughput is taken from a pass without
     if args.batched_only:  # profiling runs: the plain form's kernels would mix with the batched form's
@@ -929,6 +935,9 @@ def main() -> int:
     ap.add_argument("--batched-only", action="store_true",
                     help="mix: time the batched form only (profiling runs, where the plain form's launches of the "
                          "same kernels would mix with it)")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="mix: run the plain form only, warmup + steps decodes of the three jobs, and print no "
+                         "metric line (profiling runs of the plain form's kernels)")
     ap.add_argument("--cpu-iters", type=int, default=50, help="iterations per frame in the CPU sample")
     ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -986,6 +995,9 @@ def main() -> int:
                            args.cpu_workers)
 
     body = run_mix(args, cpu) if args.workload == "mix" else run_single(args, cpu)
+    if body.get("plain_only"):
+        print(json.dumps(body), flush=True)
+        return 0
     rec = {
         "metric": METRIC,
         "value": body.pop("value"),
